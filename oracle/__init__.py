@@ -1,0 +1,31 @@
+"""FP64 CPU oracle for the ptychography forward model, loss and gradient.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the HIP library: it is a plain, slow, NumPy complex128 implementation written
+directly from the paper's statement of the model (Eq. 1 and its composite
+form Eq. 2, Section "Universal Ptychography Algorithm based on Automatic
+Differentiation"), the loss functions named there (MSE on the modulus,
+Gaussian and Poisson maximum likelihood), and the Fourier shift theorem used
+for differentiable scan positions (Section "Benchmarking with state-of-art
+open-source ptychography algorithm").
+
+Pins (tests/test_oracle_*.py) tie it to results fixed independently of its
+own code: brute-force DFT double sums, closed-form shifts of single Fourier
+modes, Parseval, the adjoint identity of every linear operator, zero loss and
+gradient at the noiseless truth, invariance under unitary mode mixing, gauge
+identities of the gradient and central finite differences.
+"""
+
+from .model import (
+    split_positions, shift_patch, shift_patch_adjoint, propagate,
+    propagate_adjoint, resample, resample_adjoint, forward, loss_grad,
+    pointwise_loss, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN, LOSS_VJP,
+)
+
+__all__ = [
+    "split_positions", "shift_patch", "shift_patch_adjoint", "propagate",
+    "propagate_adjoint", "resample", "resample_adjoint", "forward",
+    "loss_grad", "pointwise_loss", "LOSS_AMPLITUDE", "LOSS_POISSON",
+    "LOSS_GAUSSIAN", "LOSS_VJP",
+]

@@ -1,0 +1,254 @@
+"""Plain FP64 forward model, loss and gradient (test infrastructure only).
+
+Notation follows Eq. 1: scan index k, wavelength l (L of them), illumination
+mode m (M), sample mode n (Ns), probe P_{l,m}(r), object O_{l,n}(r), scan
+position s_k, power coefficient sigma_k, background N(rho), measurement
+operator M[.].  Eq. 2 splits the model into f1 (probe power scaling by
+sigma_k), f2 (object shift by s_k), f3 (probe-object product), f4 (propagator
+D_{lambda,z}) and f5 (measurement effects and background); the functions
+below follow that order.
+
+Readings of points the paper leaves open (each one is also listed in the
+design notes):
+* s_k is the top-left corner of the probe window in object pixels and the
+  shifted object is O(r + s_k); p_k = floor(s_k + 1/2) (taken in float32, as
+  the positions are float32), delta_k = s_k - p_k in [-1/2, 1/2).
+* f2 (Fourier shift theorem): the gathered N x N patch A = O[p + r] is
+  shifted by the circular Fourier shift
+  ifft2(fft2(A) * exp(+2 pi i (f_y delta_y + f_x delta_x))), with
+  f = numpy.fft.fftfreq(N) (the Nyquist bin is -1/2).
+* f4 at wavelength lambda_l: the exit wave sits at [0, N)^2 of an
+  N_l x N_l zero array, a unitary 2D DFT is taken and the N x N bins with
+  frequencies u in [-N/2, N/2) are kept, DC at index (N/2, N/2).  N_l is an
+  input (the per-wavelength detector sampling).
+* sigma_k multiplies the field, as written in Eq. 1.
+* f5: I' = R(I + B) with R an optional bilinear resampling table (tilted
+  plane) and B the additive background; the binary mask weights the loss.
+* Losses (sum over positions and pixels, times ``scale``), eps inside:
+  amplitude (MSE on the modulus): (sqrt(I'+eps) - sqrt(Î+eps))^2;
+  Poisson: (I'+eps) - (Î+eps) ln(I'+eps);
+  Gaussian: (I' - Î)^2;
+  VJP: u * I' with u = ``measured`` an upstream gradient (mask ignored).
+* Gradients use the convention G = dL/dRe + i dL/dIm.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LOSS_AMPLITUDE = 0
+LOSS_POISSON = 1
+LOSS_GAUSSIAN = 2
+LOSS_VJP = 3
+
+
+# ----------------------------------------------------------------- f2: shift
+def split_positions(pos):
+    """Integer window corner p (int64) and sub-pixel remainder delta (float64).
+
+    The rounding is taken in float32 because the positions are float32 and
+    the GPU path takes the same decision in float32.
+    """
+    s32 = np.asarray(pos, dtype=np.float32)
+    p = np.floor(s32 + np.float32(0.5)).astype(np.int64)
+    delta = s32.astype(np.float64) - p.astype(np.float64)
+    return p, delta
+
+
+def _ramp(N: int, delta) -> np.ndarray:
+    f = np.fft.fftfreq(N)
+    ry = np.exp(2j * np.pi * f * delta[0])
+    rx = np.exp(2j * np.pi * f * delta[1])
+    return ry[:, None] * rx[None, :]
+
+
+def shift_patch(A: np.ndarray, delta) -> np.ndarray:
+    """Fourier-shift theorem: result(r) = A(r + delta) (circular)."""
+    return np.fft.ifft2(np.fft.fft2(A) * _ramp(A.shape[-1], delta))
+
+
+def shift_patch_adjoint(G: np.ndarray, delta) -> np.ndarray:
+    """Adjoint (= inverse, the shift is unitary) of ``shift_patch``."""
+    return np.fft.ifft2(np.fft.fft2(G) * np.conj(_ramp(G.shape[-1], delta)))
+
+
+# ------------------------------------------------------------ f4: propagator
+def _crop_index(N: int, nl: int) -> np.ndarray:
+    return (np.arange(N) - N // 2) % nl
+
+
+def propagate(psi: np.ndarray, nl: int) -> np.ndarray:
+    """Zero-pad the N x N exit wave to nl x nl, unitary DFT, keep N x N bins."""
+    N = psi.shape[-1]
+    if nl < N:
+        raise ValueError("pad smaller than the window")
+    z = np.zeros((nl, nl), dtype=np.complex128)
+    z[:N, :N] = psi
+    F = np.fft.fft2(z, norm="ortho")
+    idx = _crop_index(N, nl)
+    return F[np.ix_(idx, idx)]
+
+
+def propagate_adjoint(G: np.ndarray, nl: int) -> np.ndarray:
+    """Adjoint of ``propagate``: embed the bins, unitary inverse DFT, crop."""
+    N = G.shape[-1]
+    z = np.zeros((nl, nl), dtype=np.complex128)
+    idx = _crop_index(N, nl)
+    z[np.ix_(idx, idx)] = G
+    return np.fft.ifft2(z, norm="ortho")[:N, :N]
+
+
+# ------------------------------------------------------- f5: measurement side
+def resample(I: np.ndarray, idx: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """I'(a) = sum_t w[a,t] I(idx[a,t]) on a flattened N x N grid."""
+    N = I.shape[-1]
+    flat = I.reshape(N * N)
+    out = (np.asarray(w, np.float64) * flat[np.asarray(idx)]).sum(axis=1)
+    return out.reshape(N, N)
+
+
+def resample_adjoint(g: np.ndarray, idx: np.ndarray, w: np.ndarray) -> np.ndarray:
+    N = g.shape[-1]
+    out = np.zeros(N * N, dtype=np.float64)
+    np.add.at(out, np.asarray(idx).ravel(),
+              (np.asarray(w, np.float64) * g.reshape(N * N, 1)).ravel())
+    return out.reshape(N, N)
+
+
+def pointwise_loss(I: np.ndarray, meas: np.ndarray, kind: int, eps: float):
+    """Per-pixel loss and its derivative with respect to the prediction I."""
+    I = np.asarray(I, np.float64)
+    meas = np.asarray(meas, np.float64)
+    if kind == LOSS_AMPLITUDE:
+        a = np.sqrt(I + eps)
+        b = np.sqrt(meas + eps)
+        return (a - b) ** 2, 1.0 - b / a
+    if kind == LOSS_POISSON:
+        return (I + eps) - (meas + eps) * np.log(I + eps), 1.0 - (meas + eps) / (I + eps)
+    if kind == LOSS_GAUSSIAN:
+        return (I - meas) ** 2, 2.0 * (I - meas)
+    if kind == LOSS_VJP:
+        return meas * I, meas.copy()
+    raise ValueError(f"unknown loss kind {kind}")
+
+
+# ------------------------------------------------------------- shape helpers
+def _as_object(obj):
+    obj = np.asarray(obj, dtype=np.complex128)
+    if obj.ndim == 3:
+        return obj[:, None], True
+    return obj, False
+
+
+def _window(obj_ln, p, N):
+    py, px = int(p[0]), int(p[1])
+    H, W = obj_ln.shape
+    if py < 0 or px < 0 or py + N > H or px + N > W:
+        raise ValueError("probe window outside the object")
+    return obj_ln[py:py + N, px:px + N]
+
+
+# ---------------------------------------------------------------- Eq. 1 / 2
+def _exit_waves(obj, probe, pk, dk, sig, pads):
+    """Per wavelength l and sample mode n: patch A, its FFT, shifted patch,
+    and the detector fields Psi[l][n][m] of f4(f3(f1(sigma_k), f2(s_k)))."""
+    L, Ns = obj.shape[:2]
+    M, N = probe.shape[1], probe.shape[-1]
+    A, Ahat, Osh, Psi = {}, {}, {}, {}
+    for l in range(L):
+        for n in range(Ns):
+            a = _window(obj[l, n], pk, N)
+            A[l, n] = a
+            Ahat[l, n] = np.fft.fft2(a)
+            Osh[l, n] = np.fft.ifft2(Ahat[l, n] * _ramp(N, dk))
+            for m in range(M):
+                psi = sig * probe[l, m] * Osh[l, n]
+                Psi[l, n, m] = propagate(psi, pads[l])
+    return A, Ahat, Osh, Psi
+
+
+def forward(obj, probe, pos, pads, sigma=None, background=None, resample_table=None):
+    """Predicted patterns I'_k, float64 [K][N][N] (Eq. 1)."""
+    obj, _ = _as_object(obj)
+    probe = np.asarray(probe, dtype=np.complex128)
+    L, Ns = obj.shape[:2]
+    M, N = probe.shape[1], probe.shape[-1]
+    p, d = split_positions(pos)
+    K = p.shape[0]
+    out = np.empty((K, N, N), dtype=np.float64)
+    for k in range(K):
+        sig = 1.0 if sigma is None else float(sigma[k])
+        _, _, _, Psi = _exit_waves(obj, probe, p[k], d[k], sig, pads)
+        I = np.zeros((N, N))
+        for key in Psi:
+            I += np.abs(Psi[key]) ** 2
+        if background is not None:
+            I = I + np.asarray(background, np.float64)
+        if resample_table is not None:
+            I = resample(I, *resample_table)
+        out[k] = I
+    return out
+
+
+def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
+              scale=1.0, sigma=None, background=None, mask=None,
+              resample_table=None, positions=None):
+    """Loss and gradients w.r.t. object, probe, positions and sigma.
+
+    ``positions`` restricts the sums over k to a subset (the loss is a sum of
+    per-position terms, so the full gradient is the sum over a partition).
+    Returns a dict: loss (float), g_object (shape of ``obj``), g_probe
+    [L][M][N][N], g_pos [K][2], g_sigma [K] (zero outside the subset).
+    """
+    obj, squeeze = _as_object(obj)
+    probe = np.asarray(probe, dtype=np.complex128)
+    L, Ns = obj.shape[:2]
+    M, N = probe.shape[1], probe.shape[-1]
+    p, d = split_positions(pos)
+    K = p.shape[0]
+    f = np.fft.fftfreq(N)
+    w = np.ones((N, N)) if (mask is None or kind == LOSS_VJP) else np.asarray(mask, np.float64)
+    g_obj = np.zeros_like(obj)
+    g_prb = np.zeros_like(probe)
+    g_pos = np.zeros((K, 2))
+    g_sig = np.zeros(K)
+    total = 0.0
+    ks = range(K) if positions is None else positions
+    for k in ks:
+        sig = 1.0 if sigma is None else float(sigma[k])
+        A, Ahat, Osh, Psi = _exit_waves(obj, probe, p[k], d[k], sig, pads)
+        I = np.zeros((N, N))
+        for key in Psi:
+            I += np.abs(Psi[key]) ** 2
+        if background is not None:
+            I = I + np.asarray(background, np.float64)
+        Ip = resample(I, *resample_table) if resample_table is not None else I
+        ell, dell = pointwise_loss(Ip, measured[k], kind, eps)
+        total += float(np.sum(w * ell))
+        # dL/dI, pulled back through the resampling
+        g = w * dell
+        if resample_table is not None:
+            g = resample_adjoint(g, *resample_table)
+        ramp = _ramp(N, d[k])
+        for l in range(L):
+            for n in range(Ns):
+                G_osh = np.zeros((N, N), dtype=np.complex128)
+                for m in range(M):
+                    # |Psi|^2 -> Psi: G_Psi = 2 g Psi; f4 adjoint
+                    chi = propagate_adjoint(2.0 * g * Psi[l, n, m], pads[l])
+                    g_prb[l, m] += np.conj(sig * Osh[l, n]) * chi
+                    G_osh += np.conj(sig * probe[l, m]) * chi
+                    g_sig[k] += float(np.real(np.sum(np.conj(chi) * probe[l, m] * Osh[l, n])))
+                # f2 adjoint and the position derivative at fixed p
+                Ghat = np.fft.fft2(G_osh)
+                G_A = np.fft.ifft2(Ghat * np.conj(ramp))
+                py, px = int(p[k, 0]), int(p[k, 1])
+                g_obj[l, n, py:py + N, px:px + N] += G_A
+                core = np.conj(Ghat) * ramp * Ahat[l, n] * (2j * np.pi)
+                g_pos[k, 0] += float(np.real(np.sum(core * f[:, None]))) / (N * N)
+                g_pos[k, 1] += float(np.real(np.sum(core * f[None, :]))) / (N * N)
+    g_obj *= scale
+    g_prb *= scale
+    g_pos *= scale
+    g_sig *= scale
+    return dict(loss=total * scale, g_object=g_obj[:, 0] if squeeze else g_obj,
+                g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig)
