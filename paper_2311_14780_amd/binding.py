@@ -1,0 +1,295 @@
+"""ctypes binding of libptycho.so (argument marshalling only).
+
+The functions here carry the names of the C entry points declared in
+include/ptycho.h and take torch tensors that already live on the GPU; every
+step of the model, loss and gradient runs in the library's HIP kernels.
+PyTorch only supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptycho.so")
+
+MAX_WAVELENGTHS = 8
+MAX_MODES = 16
+
+PTYCHO_OK = 0
+PTYCHO_EINVAL = -1
+PTYCHO_ERANGE = -2
+PTYCHO_EUNSUPPORTED = -3
+PTYCHO_ENOSPC = -4
+PTYCHO_EHIP = -5
+
+LOSS_AMPLITUDE = 0
+LOSS_POISSON = 1
+LOSS_GAUSSIAN = 2
+LOSS_VJP = 3
+
+_c_i32 = ctypes.c_int32
+_c_p = ctypes.c_void_p
+
+
+class JobT(ctypes.Structure):
+    _fields_ = [("K", _c_i32), ("L", _c_i32), ("M", _c_i32), ("N", _c_i32), ("H", _c_i32),
+                ("W", _c_i32), ("pad", _c_i32 * MAX_WAVELENGTHS),
+                ("object", _c_p), ("probe", _c_p), ("pos", _c_p), ("sigma", _c_p),
+                ("background", _c_p), ("mask", _c_p), ("rs_idx", _c_p), ("rs_w", _c_p),
+                ("rsT_ptr", _c_p), ("rsT_col", _c_p), ("rsT_val", _c_p), ("measured", _c_p)]
+
+
+class LossT(ctypes.Structure):
+    _fields_ = [("kind", _c_i32), ("eps", ctypes.c_float), ("scale", ctypes.c_float)]
+
+
+class GradsT(ctypes.Structure):
+    _fields_ = [("loss", _c_p), ("g_object", _c_p), ("g_probe", _c_p), ("g_pos", _c_p),
+                ("g_sigma", _c_p)]
+
+
+class AdamT(ctypes.Structure):
+    _fields_ = [("m_object", _c_p), ("v_object", _c_p), ("m_probe", _c_p), ("v_probe", _c_p),
+                ("m_pos", _c_p), ("v_pos", _c_p), ("lr_object", ctypes.c_float),
+                ("lr_probe", ctypes.c_float), ("lr_pos", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("t", _c_i32)]
+
+
+class PtychoError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {error_string(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2311_14780_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ptycho_supported.argtypes = [_c_i32, _c_i32]
+        L.ptycho_supported.restype = _c_i32
+        L.ptycho_workspace_bytes.argtypes = [ctypes.POINTER(JobT), _c_i32, _c_i32, _c_i32,
+                                             ctypes.POINTER(ctypes.c_size_t)]
+        L.ptycho_workspace_bytes.restype = _c_i32
+        L.ptycho_forward.argtypes = [ctypes.POINTER(JobT), _c_i32, ctypes.POINTER(_c_p), _c_p,
+                                     ctypes.c_size_t, _c_p]
+        L.ptycho_forward.restype = _c_i32
+        L.ptycho_loss_grad.argtypes = [ctypes.POINTER(JobT), _c_i32, ctypes.POINTER(LossT),
+                                       ctypes.POINTER(GradsT), _c_p, ctypes.c_size_t, _c_p]
+        L.ptycho_loss_grad.restype = _c_i32
+        L.ptycho_step.argtypes = [ctypes.POINTER(JobT), _c_i32, ctypes.POINTER(LossT),
+                                  ctypes.POINTER(GradsT), ctypes.POINTER(AdamT), _c_p,
+                                  ctypes.c_size_t, _c_p]
+        L.ptycho_step.restype = _c_i32
+        L.ptycho_status.argtypes = [_c_p, _c_i32, _c_p]
+        L.ptycho_status.restype = _c_i32
+        L.ptycho_transpose_table.argtypes = [_c_p, _c_p, _c_i32, _c_i32, _c_p, _c_p, _c_p]
+        L.ptycho_transpose_table.restype = _c_i32
+        L.ptycho_error_string.argtypes = [_c_i32]
+        L.ptycho_error_string.restype = ctypes.c_char_p
+        L.ptycho_release.argtypes = []
+        L.ptycho_release.restype = None
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().ptycho_error_string(int(code)).decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Problem:
+    """Device tensors of one reconstruction job (the variables of Eq. 1).
+
+    object complex64 [L][H][W]; probe complex64 [L][M][N][N]; pos float32
+    [K][2]; pads: DFT size per wavelength; measured float32 [K][N][N];
+    sigma float32 [K]; background float32 [N][N]; mask uint8 [N][N];
+    resample: (idx int32 [N*N][4], w float32 [N*N][4], ptr, col, val) on
+    the device, see ``resample_tables``.
+    """
+    object: torch.Tensor
+    probe: torch.Tensor
+    pos: torch.Tensor
+    pads: Sequence[int]
+    measured: Optional[torch.Tensor] = None
+    sigma: Optional[torch.Tensor] = None
+    background: Optional[torch.Tensor] = None
+    mask: Optional[torch.Tensor] = None
+    resample: Optional[tuple] = None
+
+    @property
+    def K(self):
+        return int(self.pos.shape[0])
+
+    @property
+    def L(self):
+        return int(self.probe.shape[0])
+
+    @property
+    def M(self):
+        return int(self.probe.shape[1])
+
+    @property
+    def N(self):
+        return int(self.probe.shape[-1])
+
+    def to_job(self) -> JobT:
+        j = JobT()
+        j.K, j.L, j.M, j.N = self.K, self.L, self.M, self.N
+        j.H, j.W = int(self.object.shape[-2]), int(self.object.shape[-1])
+        if len(self.pads) != self.L:
+            raise ValueError("one pad per wavelength is required")
+        for l, p in enumerate(self.pads):
+            j.pad[l] = int(p)
+        j.object = _ptr(self.object)
+        j.probe = _ptr(self.probe)
+        j.pos = _ptr(self.pos)
+        j.sigma = _ptr(self.sigma)
+        j.background = _ptr(self.background)
+        j.mask = _ptr(self.mask)
+        if self.resample is not None:
+            idx, w, ptr, col, val = self.resample
+            j.rs_idx, j.rs_w = _ptr(idx), _ptr(w)
+            j.rsT_ptr, j.rsT_col, j.rsT_val = _ptr(ptr), _ptr(col), _ptr(val)
+        j.measured = _ptr(self.measured)
+        return j
+
+
+def _jobs(problems: Sequence[Problem]):
+    arr = (JobT * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p.to_job()
+    return arr
+
+
+def ptycho_supported(N: int, pad: int) -> bool:
+    return bool(lib().ptycho_supported(int(N), int(pad)))
+
+
+def ptycho_workspace_bytes(problems: Sequence[Problem], which: int = 1, chunk: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    code = lib().ptycho_workspace_bytes(_jobs(problems), len(problems), int(which), int(chunk),
+                                        ctypes.byref(out))
+    if code:
+        raise PtychoError(code, "ptycho_workspace_bytes")
+    return int(out.value)
+
+
+def ptycho_forward(problems: Sequence[Problem], intensities: Sequence[torch.Tensor],
+                   workspace: torch.Tensor, stream=None) -> None:
+    outs = (_c_p * len(problems))(*[t.data_ptr() for t in intensities])
+    code = lib().ptycho_forward(_jobs(problems), len(problems), outs, _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream))
+    if code:
+        raise PtychoError(code, "ptycho_forward")
+
+
+def _grads_array(grads: Sequence[dict]):
+    arr = (GradsT * len(grads))()
+    for i, g in enumerate(grads):
+        arr[i].loss = _ptr(g.get("loss"))
+        arr[i].g_object = _ptr(g.get("g_object"))
+        arr[i].g_probe = _ptr(g.get("g_probe"))
+        arr[i].g_pos = _ptr(g.get("g_pos"))
+        arr[i].g_sigma = _ptr(g.get("g_sigma"))
+    return arr
+
+
+def ptycho_loss_grad(problems: Sequence[Problem], grads: Sequence[dict], kind: int = 0,
+                     eps: float = 1e-6, scale: float = 1.0, workspace: torch.Tensor = None,
+                     stream=None) -> None:
+    loss = LossT(int(kind), float(eps), float(scale))
+    code = lib().ptycho_loss_grad(_jobs(problems), len(problems), ctypes.byref(loss),
+                                  _grads_array(grads), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), _stream(stream))
+    if code:
+        raise PtychoError(code, "ptycho_loss_grad")
+
+
+def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequence[dict],
+                kind: int = 0, eps: float = 1e-6, scale: float = 1.0,
+                workspace: torch.Tensor = None, stream=None) -> None:
+    loss = LossT(int(kind), float(eps), float(scale))
+    arr = (AdamT * len(adam))()
+    for i, a in enumerate(adam):
+        arr[i].m_object, arr[i].v_object = _ptr(a.get("m_object")), _ptr(a.get("v_object"))
+        arr[i].m_probe, arr[i].v_probe = _ptr(a.get("m_probe")), _ptr(a.get("v_probe"))
+        arr[i].m_pos, arr[i].v_pos = _ptr(a.get("m_pos")), _ptr(a.get("v_pos"))
+        arr[i].lr_object = float(a.get("lr_object", 0.0))
+        arr[i].lr_probe = float(a.get("lr_probe", 0.0))
+        arr[i].lr_pos = float(a.get("lr_pos", 0.0))
+        arr[i].beta1 = float(a.get("beta1", 0.9))
+        arr[i].beta2 = float(a.get("beta2", 0.999))
+        arr[i].eps = float(a.get("eps", 1e-8))
+        arr[i].t = int(a["t"])
+    code = lib().ptycho_step(_jobs(problems), len(problems), ctypes.byref(loss),
+                             _grads_array(grads), arr, _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream(stream))
+    if code:
+        raise PtychoError(code, "ptycho_step")
+
+
+def ptycho_status(workspace: torch.Tensor, job: int = 0, stream=None) -> int:
+    return int(lib().ptycho_status(_ptr(workspace), int(job), _stream(stream)))
+
+
+def ptycho_transpose_table(idx, w, n_in: int):
+    """CSR transpose of a host resampling table (numpy int32/float32 [n_out][4])."""
+    import numpy as np
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    n_out = idx.shape[0]
+    ptr = np.zeros(n_in + 1, np.int32)
+    col = np.zeros(4 * n_out, np.int32)
+    val = np.zeros(4 * n_out, np.float32)
+    code = lib().ptycho_transpose_table(idx.ctypes.data, w.ctypes.data, n_out, n_in,
+                                        ptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+    if code:
+        raise PtychoError(code, "ptycho_transpose_table")
+    return ptr, col, val
+
+
+def ptycho_release() -> None:
+    lib().ptycho_release()
+
+
+def resample_tables(idx, w, device) -> tuple:
+    """Device copies of a resampling table and of its CSR transpose."""
+    import numpy as np
+    n = idx.shape[0]
+    ptr, col, val = ptycho_transpose_table(idx, w, n)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return (to(np.asarray(idx, np.int32)), to(np.asarray(w, np.float32)), to(ptr), to(col), to(val))
+
+
+def workspace(problems: Sequence[Problem], which: int = 1, chunk: int = 0,
+              device=None) -> torch.Tensor:
+    nbytes = ptycho_workspace_bytes(problems, which, chunk)
+    dev = device if device is not None else problems[0].object.device
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)

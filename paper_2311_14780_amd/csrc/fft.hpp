@@ -1,0 +1,366 @@
+// fft.hpp - LDS-resident mixed-radix Stockham FFTs for gfx950 (wave64).
+//
+// A workgroup transforms LINES lines of length n at once.  The length and its
+// radix plan are compile-time constants, so every butterfly, twiddle index and
+// LDS address is resolved by the compiler.  Each pass reads all of its inputs
+// into registers, synchronises, and writes its outputs back in place (one LDS
+// buffer, no ping-pong), so the whole FFT needs n * LINES complex words of LDS.
+// The first pass may take its inputs from a caller functor (global memory with
+// zero padding, fused pointwise products) and the last pass hands its outputs
+// to a caller functor (cropping, scaling, fused products, global stores).
+//
+// Stockham autosort (natural-order output) for pass radix R with Ns = product
+// of earlier radices: butterfly j reads x[j + r n/R], multiplies by
+// w_{Ns R}^{r (j mod Ns)}, takes a length-R DFT and writes
+// y[(j / Ns) Ns R + (j mod Ns) + r Ns].  Twiddles come from a table
+// T_n[t] = exp(-2 pi i t / n) computed in float64 on the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ptycho {
+
+// ----------------------------------------------------------- complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulconj(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 cmul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------ compile-time cos / sin table
+// Taylor series in float64 after reduction to [-pi, pi]; used only in constant
+// expressions (radix constants), never at run time.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ct_reduce(double x) {
+  while (x > kPi) x -= 2.0 * kPi;
+  while (x < -kPi) x += 2.0 * kPi;
+  return x;
+}
+constexpr double ct_sin(double x) {
+  x = ct_reduce(x);
+  double term = x, sum = x;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos(double x) {
+  x = ct_reduce(x);
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// c[j] = cos(2 pi j / R), s[j] = sin(2 pi j / R)
+template <int R>
+struct Roots {
+  float c[R];
+  float s[R];
+  constexpr Roots() : c(), s() {
+    for (int j = 0; j < R; ++j) {
+      c[j] = static_cast<float>(ct_cos(2.0 * kPi * j / R));
+      s[j] = static_cast<float>(ct_sin(2.0 * kPi * j / R));
+    }
+  }
+};
+
+// --------------------------------------------------------- small DFT kernels
+// In-place length-R DFT, forward (exp(-2 pi i k r / R)) or inverse (exp(+...)).
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    float2 t2 = cadd(v[1], v[3]), t3 = cmul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+// Odd prime R (3, 5, 7): symmetric/antisymmetric pairs.
+template <int R, bool INV>
+struct DftOdd {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr int h = (R - 1) / 2;
+    constexpr Roots<R> w{};
+    float2 sp[h], sm[h];
+#pragma unroll
+    for (int r = 1; r <= h; ++r) {
+      sp[r - 1] = cadd(v[r], v[R - r]);
+      sm[r - 1] = csub(v[r], v[R - r]);
+    }
+    float2 out[R];
+    float2 y0 = v[0];
+#pragma unroll
+    for (int r = 0; r < h; ++r) y0 = cadd(y0, sp[r]);
+    out[0] = y0;
+#pragma unroll
+    for (int k = 1; k <= h; ++k) {
+      float2 a = v[0];
+      float2 b = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 1; r <= h; ++r) {
+        const int j = (k * r) % R;
+        a.x = fmaf(sp[r - 1].x, w.c[j], a.x);
+        a.y = fmaf(sp[r - 1].y, w.c[j], a.y);
+        b.x = fmaf(sm[r - 1].x, w.s[j], b.x);
+        b.y = fmaf(sm[r - 1].y, w.s[j], b.y);
+      }
+      // forward: y_k = a - i b, y_{R-k} = a + i b
+      const float2 mib = cmul_mi<INV>(b);
+      out[k] = cadd(a, mib);
+      out[R - k] = csub(a, mib);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = out[r];
+  }
+};
+
+template <bool INV> struct Dft<3, INV> : DftOdd<3, INV> {};
+template <bool INV> struct Dft<5, INV> : DftOdd<5, INV> {};
+template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
+
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr float h = 0.70710678118654752440f;
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    // o[k] *= w8^k ; w8 = exp(-+ 2 pi i / 8)
+    const float sg = INV ? 1.f : -1.f;
+    float2 o1 = make_float2(h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x));
+    float2 o2 = cmul_mi<INV>(o[2]);
+    float2 o3 = make_float2(h * (-o[3].x - sg * o[3].y), h * (-o[3].y + sg * o[3].x));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// Composite R = R1 * R2 by one decimation-in-time step:
+// y[k1 + R1 k2] = sum_{n2} w_R^{n2 k1} w_R2^{n2 k2} DFT_R1(v[R2 n1 + n2])[k1].
+template <int R1, int R2, bool INV>
+struct DftComposite {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr int R = R1 * R2;
+    constexpr Roots<R> w{};
+    float2 e[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) e[n2][n1] = v[R2 * n1 + n2];
+      Dft<R1, INV>::run(e[n2]);
+#pragma unroll
+      for (int k1 = 1; k1 < R1; ++k1) {
+        const int j = (n2 * k1) % R;
+        if (j != 0) {
+          const float2 tw = make_float2(w.c[j], INV ? w.s[j] : -w.s[j]);
+          e[n2][k1] = cmul(e[n2][k1], tw);
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = e[n2][k1];
+      Dft<R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftComposite<2, 3, INV> {};
+template <bool INV> struct Dft<9, INV> : DftComposite<3, 3, INV> {};
+template <bool INV> struct Dft<10, INV> : DftComposite<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftComposite<4, 3, INV> {};
+template <bool INV> struct Dft<14, INV> : DftComposite<2, 7, INV> {};
+template <bool INV> struct Dft<15, INV> : DftComposite<3, 5, INV> {};
+template <bool INV> struct Dft<16, INV> : DftComposite<4, 4, INV> {};
+
+// ------------------------------------------------------------- radix plans
+template <int... Rs>
+struct Radices {};
+
+template <int n>
+struct Plan;  // Plan<n>::type = Radices<...>, product n
+
+#define PTYCHO_PLAN(n, ...) \
+  template <>               \
+  struct Plan<n> {          \
+    using type = Radices<__VA_ARGS__>; \
+  };
+
+PTYCHO_PLAN(64, 8, 8)
+PTYCHO_PLAN(72, 8, 9)
+PTYCHO_PLAN(80, 16, 5)
+PTYCHO_PLAN(84, 12, 7)
+PTYCHO_PLAN(90, 9, 10)
+PTYCHO_PLAN(96, 8, 12)
+PTYCHO_PLAN(128, 16, 8)
+PTYCHO_PLAN(140, 10, 14)
+PTYCHO_PLAN(150, 10, 15)
+PTYCHO_PLAN(168, 12, 14)
+PTYCHO_PLAN(189, 7, 3, 9)
+PTYCHO_PLAN(256, 16, 16)
+PTYCHO_PLAN(280, 8, 5, 7)
+PTYCHO_PLAN(300, 12, 5, 5)
+PTYCHO_PLAN(315, 9, 5, 7)
+PTYCHO_PLAN(336, 16, 3, 7)
+PTYCHO_PLAN(343, 7, 7, 7)
+PTYCHO_PLAN(375, 15, 5, 5)
+PTYCHO_PLAN(384, 16, 8, 3)
+PTYCHO_PLAN(420, 12, 5, 7)
+PTYCHO_PLAN(480, 16, 6, 5)
+PTYCHO_PLAN(512, 8, 8, 8)
+PTYCHO_PLAN(560, 16, 5, 7)
+PTYCHO_PLAN(600, 12, 10, 5)
+PTYCHO_PLAN(675, 9, 15, 5)
+PTYCHO_PLAN(750, 10, 15, 5)
+#undef PTYCHO_PLAN
+
+// ------------------------------------------------------ the Stockham engine
+// Layout of element i of line `line` in the LDS buffer.
+//  LINE_FAST = true : buf[i * LP + line]  (column groups: lanes walk lines;
+//                     LP = lines + 1)
+//  LINE_FAST = false: buf[line * LP + i + i / 16]  (rows: lanes walk elements;
+//                     one skew word per 16 keeps radix-16 strided writes
+//                     spread over the LDS banks; LP >= row_lp(n))
+template <int LINES, int LP, bool LINE_FAST>
+struct Lds {
+  __device__ __forceinline__ static int at(int line, int i) {
+    return LINE_FAST ? i * LP + line : line * LP + i + (i >> 4);
+  }
+};
+constexpr int row_lp(int n) { return n + (n >> 4) + 1; }
+
+// One Stockham pass.  FIRST: inputs from `load(line, i)`; otherwise from LDS.
+// LAST: outputs to `store(line, i, v)`; otherwise to LDS.
+template <int n, int R, int Ns, bool FIRST, bool LAST, bool INV, int LINES, int NT, int LP,
+          bool LINE_FAST, class Load, class Store>
+__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw,
+                                              const Load& load, const Store& store) {
+  constexpr int NB = n / R;             // butterflies per line
+  constexpr int BF = LINES * NB;        // butterflies per pass
+  constexpr int ITER = (BF + NT - 1) / NT;
+  using Ix = Lds<LINES, LP, LINE_FAST>;
+  const int tid = threadIdx.x;
+  float2 v[ITER][R];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int b = tid + it * NT;
+    if ((BF % NT == 0) || b < BF) {
+      const int line = LINE_FAST ? (b % LINES) : (b / NB);
+      const int j = LINE_FAST ? (b / LINES) : (b % NB);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = j + r * NB;
+        v[it][r] = FIRST ? load(line, i) : buf[Ix::at(line, i)];
+      }
+      if (Ns > 1) {
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * (n / (Ns * R))];
+          if (INV) w.y = -w.y;
+          v[it][r] = cmul(v[it][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[it]);
+    }
+  }
+  __syncthreads();  // every read of this pass precedes any write (in-place LDS)
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int b = tid + it * NT;
+    if ((BF % NT == 0) || b < BF) {
+      const int line = LINE_FAST ? (b % LINES) : (b / NB);
+      const int j = LINE_FAST ? (b / LINES) : (b % NB);
+      const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int o = base + r * Ns;
+        if (LAST)
+          store(line, o, v[it][r]);
+        else
+          buf[Ix::at(line, o)] = v[it][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int n, int Ns, bool FIRST, bool INV, int LINES, int NT, int LP, bool LINE_FAST,
+          class Load, class Store, int R, int... Rest>
+__device__ __forceinline__ void stockham_run(float2* buf, const float2* __restrict__ tw,
+                                             const Load& load, const Store& store,
+                                             Radices<R, Rest...>) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  stockham_pass<n, R, Ns, FIRST, LAST, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store);
+  if constexpr (!LAST) {
+    stockham_run<n, Ns * R, false, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
+                                                                   Radices<Rest...>{});
+  }
+}
+
+// Full FFT of LINES lines of length n: inputs via load(line, i) (i in [0, n)),
+// outputs via store(line, i, value).  `buf` must hold LINES * n elements laid
+// out as Lds<LINES, LP, LINE_FAST>.  The call begins with the first pass's
+// reads (the caller must have synchronised any earlier use of `buf`) and ends
+// with a workgroup barrier.  Unnormalised in both directions.
+template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Load, class Store>
+__device__ __forceinline__ void fft_lines(float2* buf, const float2* __restrict__ tw,
+                                          const Load& load, const Store& store) {
+  // The twiddle base is made opaque here so that the compiler cannot hoist
+  // the (loop-invariant) twiddle loads of an FFT out of an enclosing loop,
+  // which would pin every twiddle value in registers for the whole loop.
+  {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(tw);
+    unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    tw = reinterpret_cast<const float2*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  }
+  stockham_run<n, 1, true, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
+                                                           typename Plan<n>::type{});
+}
+
+}  // namespace ptycho

@@ -1,0 +1,140 @@
+"""The C ABI library loads, exports every declared symbol and validates its
+arguments on the host (CPU only: no kernel is launched here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptycho.h")
+
+B = pytest.importorskip("paper_2311_14780_amd.binding")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(ptycho_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = _declared()
+    assert len(names) >= 9
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (ptycho_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        getattr(lib, n)
+
+
+def test_error_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert B.error_string(code)
+    assert "unknown" in B.error_string(-99)
+
+
+def test_supported_sizes():
+    for N, pads in ((64, (64, 72, 80, 84, 90, 96)), (256, (256, 280, 315, 343)),
+                    (384, (384, 420, 480)), (512, (512, 560, 600, 675, 750)),
+                    (128, (128, 140, 150, 168, 189))):
+        for p in pads:
+            assert B.ptycho_supported(N, p)
+    assert not B.ptycho_supported(256, 257)
+    assert not B.ptycho_supported(100, 100)
+
+
+def _job(K=4, L=2, M=3, N=64, H=128, W=128, pads=(64, 80)):
+    j = B.JobT()
+    j.K, j.L, j.M, j.N, j.H, j.W = K, L, M, N, H, W
+    for l, p in enumerate(pads):
+        j.pad[l] = p
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    j.object = j.probe = j.pos = j.measured = fake
+    return j
+
+
+def _ws_bytes(j, which=1, chunk=0):
+    out = ctypes.c_size_t(0)
+    code = B.lib().ptycho_workspace_bytes(ctypes.byref(j), 1, which, chunk, ctypes.byref(out))
+    return code, out.value
+
+
+def test_workspace_bytes_scale_with_chunk():
+    j = _job()
+    c_all, b_all = _ws_bytes(j)
+    c_one, b_one = _ws_bytes(j, chunk=1)
+    assert c_all == 0 and c_one == 0
+    assert b_all > b_one > 0
+    # per position: X, GX (L N^2 c64 each), Y (L M N^2 c64), ramps, partials
+    per = 8 * 64 * 64 * (2 * 2 + 2 * 3)
+    assert b_all - b_one >= 3 * per
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(L=0), B.PTYCHO_EINVAL), (dict(L=9), B.PTYCHO_EINVAL), (dict(M=0), B.PTYCHO_EINVAL),
+    (dict(K=-1), B.PTYCHO_EINVAL), (dict(N=100), B.PTYCHO_EUNSUPPORTED),
+    (dict(H=32), B.PTYCHO_ERANGE), (dict(pads=(64, 63)), B.PTYCHO_ERANGE),
+    (dict(pads=(64, 81)), B.PTYCHO_EUNSUPPORTED)])
+def test_invalid_jobs_rejected_on_host(change, code):
+    kw = dict(K=4, L=2, M=3, N=64, H=128, W=128, pads=(64, 80))
+    kw.update(change)
+    j = _job(**kw)
+    assert _ws_bytes(j)[0] == code
+    loss = B.LossT(0, 1e-6, 1.0)
+    grads = B.GradsT()
+    rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                                  ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == code
+
+
+def test_null_pointers_rejected():
+    j = _job()
+    j.object = None
+    assert _ws_bytes(j)[0] == B.PTYCHO_EINVAL
+    j = _job()
+    j.measured = None
+    loss = B.LossT(0, 1e-6, 1.0)
+    grads = B.GradsT()
+    rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                                  ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == B.PTYCHO_EINVAL
+    rc = B.lib().ptycho_loss_grad(None, 1, ctypes.byref(loss), ctypes.byref(grads),
+                                  ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == B.PTYCHO_EINVAL
+
+
+def test_partial_resample_table_rejected():
+    j = _job()
+    j.rs_idx = ctypes.c_void_p(0x3000)
+    assert _ws_bytes(j)[0] == B.PTYCHO_EINVAL
+
+
+def test_transpose_table_matches_oracle_adjoint():
+    from oracle import model as om
+    from synth.tilt import tilt_table
+    N = 64
+    idx, w, mask = tilt_table(N)
+    ptr, col, val = B.ptycho_transpose_table(idx, w, N * N)
+    assert ptr[0] == 0 and ptr[-1] == int(np.count_nonzero(w))
+    g = np.random.default_rng(0).normal(size=(N, N))
+    out = np.zeros(N * N)
+    for j in range(N * N):
+        s, e = ptr[j], ptr[j + 1]
+        out[j] = np.sum(val[s:e].astype(np.float64) * g.ravel()[col[s:e]])
+    ref = om.resample_adjoint(g, idx, w)
+    assert np.allclose(out.reshape(N, N), ref, rtol=1e-12, atol=1e-12)
+    # columns ascend inside each row (fixed summation order)
+    for j in range(0, N * N, 97):
+        s, e = ptr[j], ptr[j + 1]
+        assert np.all(np.diff(col[s:e]) >= 0)
+
+
+def test_transpose_table_rejects_bad_index():
+    idx = np.array([[0, 1, 2, 99]], np.int32)
+    w = np.full((1, 4), 0.25, np.float32)
+    with pytest.raises(B.PtychoError):
+        B.ptycho_transpose_table(idx, w, 4)
