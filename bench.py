@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the ptychography loss + gradient iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload C2]
+
+One step is one pass of the whole hot path over the workload: positions ->
+object patches -> sub-pixel Fourier shift -> probe modes -> per-wavelength
+padded DFT -> incoherent sum -> loss -> hand-written adjoint -> object,
+probe, position and power-coefficient gradients -> Adam update of object,
+probe and positions (``ptycho_step``).  All inputs are seeded synthetic data
+resident in HBM before the timed region starts; the measured patterns are
+Poisson draws from the model's own forward pass of the ground truth.
+
+Prints one JSON line.  ``value`` is pattern-modes per second (one pattern-mode
+is one (position, wavelength, probe mode) propagation, forward and adjoint).
+``roofline`` reports the kernel class with the largest GPU time: algorithmic
+HBM bytes per launch / average launch duration (HIP events on the launch
+stream, over the timed region) against the 8 TB/s HBM3E peak.
+``cpu_baseline`` times the FP64 oracle on a bounded sample of positions.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pattern-modes/s for loss+gradient iteration (%HBM roofline); serving p50/p99"
+
+
+def alg_bytes(kernel: str, K: int, L: int, M: int, N: int, H: int, W: int) -> float:
+    """Algorithmic HBM bytes of one step attributed to a kernel class.
+
+    Per (position, wavelength): object gather 8N^2, object-gradient
+    contribution 8N^2, forward shift transpose 16N^2 (write + read), adjoint
+    shift transpose 16N^2; per (position, wavelength, mode): column-pass
+    output written and read 16N^2, detector-pass output written and read
+    16N^2; per position: measured pattern 4N^2; state: probe and object read
+    plus gradient write 16 L (M N^2 + H W); Adam: 28 bytes per real
+    coordinate of object, probe and positions.
+    """
+    n2 = float(N) * N
+    kl, klm = K * L, K * L * M
+    table = {
+        "row_fwd": kl * 16 * n2,                               # gather + X write
+        "col_fwd": kl * 8 * n2 + klm * 8 * n2 + L * M * 8 * n2,  # X read + Y write + probe read
+        "det": klm * 16 * n2 + K * 4 * n2,                     # Y read + Z write + measured
+        "col_adj": klm * 8 * n2 + kl * 8 * n2 + L * M * 8 * n2,  # Z read + GX write + probe read
+        "row_adj": kl * 8 * n2,                                # GX read
+        "obj_gather": kl * 8 * n2 + L * 16.0 * H * W,          # contribution + object r/w
+        "probe_reduce": L * M * 8 * n2,                        # probe gradient write
+        "adam": 28.0 * (2 * L * H * W + 2 * L * M * n2 + 2 * K),
+    }
+    return table.get(kernel, 0.0)
+
+
+def step_alg_bytes(K, L, M, N, H, W) -> float:
+    return sum(alg_bytes(k, K, L, M, N, H, W) for k in
+               ("row_fwd", "col_fwd", "det", "col_adj", "row_adj", "obj_gather", "probe_reduce", "adam"))
+
+
+def build_inputs(w, device):
+    import torch
+    import synth
+    from paper_2311_14780_amd import binding as B
+    truth = synth.make_truth(w)
+    start = synth.make_start(truth, w)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    res = None
+    if truth["resample"] is not None:
+        res = B.resample_tables(truth["resample"][0], truth["resample"][1], device)
+    mask = None if truth["mask"] is None else t(truth["mask"])
+    # simulate the measurement with the model itself on the ground truth
+    tprob = B.Problem(object=t(truth["object"][:, 0].astype(np.complex64)),
+                      probe=t(truth["probe"].astype(np.complex64)), pos=t(truth["pos"]),
+                      pads=truth["pads"], mask=mask, resample=res)
+    I = torch.empty(w.K, w.N, w.N, device=device)
+    ws = B.workspace([tprob], 0, 64)
+    B.ptycho_forward([tprob], [I], ws)
+    torch.cuda.synchronize()
+    meas = synth.sample_counts(I.cpu().numpy(), w.seed)
+    del ws, tprob, I
+    prob = B.Problem(object=t(start["object"][:, 0].astype(np.complex64)),
+                     probe=t(start["probe"].astype(np.complex64)), pos=t(start["pos"]),
+                     pads=start["pads"], measured=t(meas), mask=mask, resample=res)
+    return truth, start, prob
+
+
+def cpu_baseline(w, truth, start, budget_s: float = 12.0, max_positions: int = 256):
+    """FP64 oracle loss + gradient on the first positions of the workload,
+    one position at a time until the time budget is spent."""
+    import oracle
+    import synth
+    obj = start["object"].astype(np.complex64).astype(np.complex128)
+    prb = start["probe"].astype(np.complex64).astype(np.complex128)
+    n_pre = max_positions
+    I = oracle.forward(truth["object"], truth["probe"], truth["pos"][:n_pre], truth["pads"],
+                       resample_table=truth["resample"])
+    meas = synth.sample_counts(I, w.seed)
+    elapsed, done = 0.0, 0
+    while done < n_pre and (elapsed < budget_s or done < 2):
+        t0 = time.perf_counter()
+        oracle.loss_grad(obj, prb, start["pos"][:n_pre], start["pads"], meas,
+                         mask=truth["mask"], resample_table=truth["resample"], positions=[done])
+        elapsed += time.perf_counter() - t0
+        done += 1
+    pm = done * w.L * w.M * w.Ns
+    return dict(value=pm / elapsed, unit="pattern-modes/s", cores=1, kind="oracle",
+                sample=(f"{done} of {w.K} positions of {w.name} at full N/L/M, amplitude loss + "
+                        f"object/probe/position/sigma gradients, FP64 NumPy (pocketfft), one "
+                        f"process, {elapsed:.1f} s; host has {os.cpu_count()} logical CPUs"))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU position-sharded design is not built)", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_2311_14780_amd import binding as B
+
+    w = synth.get_workload(args.workload)
+    dev = torch.device("cuda:0")
+    truth, start, prob = build_inputs(w, dev)
+    K, L, M, N, H, W = w.K, w.L, w.M, w.N, w.H, w.W
+    g = dict(loss=torch.zeros(1, device=dev), g_object=torch.zeros_like(prob.object),
+             g_probe=torch.zeros_like(prob.probe), g_pos=torch.zeros(K, 2, device=dev),
+             g_sigma=torch.zeros(K, device=dev))
+    zeros = lambda x: torch.zeros(x.numel() * (2 if x.is_complex() else 1), device=dev)
+    adam = dict(m_object=zeros(prob.object), v_object=zeros(prob.object),
+                m_probe=zeros(prob.probe), v_probe=zeros(prob.probe),
+                m_pos=zeros(prob.pos), v_pos=zeros(prob.pos),
+                lr_object=1e-3, lr_probe=1e-3, lr_pos=5e-3, t=0)
+    ws = B.workspace([prob], 2)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        adam["t"] += 1
+        B.ptycho_step([prob], [g], [adam], kind=B.LOSS_AMPLITUDE, eps=1e-6, scale=1.0,
+                      workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_kernel_timing:
+        B.ptycho_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if not args.no_kernel_timing:
+        kern = B.ptycho_profile_read()
+        B.ptycho_profile(False)
+    status = B.ptycho_status(ws, 0)
+    if status != 0:
+        print(f"device status {status}: a window left the object", file=sys.stderr)
+        return 1
+    ms = (t1 - t0) * 1e3 / args.steps
+    pm = K * L * M * w.Ns
+    value = pm / (ms * 1e-3)
+    b_step = step_alg_bytes(K, L, M, N, H, W)
+
+    roof = None
+    kern_out = {}
+    if kern:
+        for name, (tot, n) in kern.items():
+            if n:
+                kern_out[name] = dict(ms_per_step=tot / args.steps, launches_per_step=n / args.steps,
+                                      avg_launch_us=1e3 * tot / n)
+        dom = max(kern_out, key=lambda k: kern_out[k]["ms_per_step"])
+        d = kern_out[dom]
+        per_launch = alg_bytes(dom, K, L, M, N, H, W) / d["launches_per_step"]
+        achieved = per_launch / (d["avg_launch_us"] * 1e-6) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    alg_bytes_per_launch=per_launch, avg_launch_us=round(d["avg_launch_us"], 2))
+        for name, d in kern_out.items():
+            b = alg_bytes(name, K, L, M, N, H, W)
+            if b:
+                d["alg_GBps"] = round(b / (d["ms_per_step"] * 1e-3) / 1e9, 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, truth, start)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "pattern-modes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{w.name}: {L} wavelengths (harmonics {'/'.join(map(str, w.harmonics))}) "
+                                f"x {M} probe modes, probe {N}x{N}, object {H}x{W} per wavelength, "
+                                f"{K} positions ({w.scan}), pads {'/'.join(map(str, prob.pads))}, "
+                                f"{w.photons:.0e} photons/pattern; step = loss + gradients + Adam"),
+                   "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": list(prob.pads),
+                   "parallelism": "single GPU"},
+        "step_roofline": {"alg_bytes_per_step": b_step,
+                          "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),
+                          "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kern_out,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

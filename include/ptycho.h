@@ -174,6 +174,18 @@ int32_t ptycho_status(const void* workspace, int32_t job, void* stream);
 int32_t ptycho_transpose_table(const int32_t* idx, const float* w, int32_t n_out, int32_t n_in,
                                int32_t* ptr, int32_t* col, float* val);
 
+/* Per-kernel-class timing, for measurement (not needed for computation).
+   ptycho_profile(1) clears the totals and starts bracketing every launch of
+   every call with two HIP events on its stream; ptycho_profile(0) stops.
+   ptycho_profile_read() waits for the recorded launches and returns the
+   summed GPU milliseconds and the launch count of one kernel class
+   (0 <= kernel_class < number of classes; ptycho_kernel_class_name() gives
+   its name and returns NULL past the last class).  Not thread-safe against
+   concurrent calls on other host threads while enabled. */
+int32_t ptycho_profile(int32_t enable);
+int32_t ptycho_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches);
+const char* ptycho_kernel_class_name(int32_t kernel_class);
+
 /* Static description of an error code. */
 const char* ptycho_error_string(int32_t code);
 

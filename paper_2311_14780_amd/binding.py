@@ -101,6 +101,13 @@ def lib():
         L.ptycho_error_string.restype = ctypes.c_char_p
         L.ptycho_release.argtypes = []
         L.ptycho_release.restype = None
+        L.ptycho_profile.argtypes = [_c_i32]
+        L.ptycho_profile.restype = _c_i32
+        L.ptycho_profile_read.argtypes = [_c_i32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        L.ptycho_profile_read.restype = _c_i32
+        L.ptycho_kernel_class_name.argtypes = [_c_i32]
+        L.ptycho_kernel_class_name.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -277,6 +284,30 @@ def ptycho_transpose_table(idx, w, n_in: int):
 
 def ptycho_release() -> None:
     lib().ptycho_release()
+
+
+def ptycho_profile(enable: bool) -> None:
+    code = lib().ptycho_profile(1 if enable else 0)
+    if code:
+        raise PtychoError(code, "ptycho_profile")
+
+
+def ptycho_profile_read() -> dict:
+    """{kernel class name: (total ms, launches)} since ptycho_profile(True)."""
+    out = {}
+    i = 0
+    while True:
+        name = lib().ptycho_kernel_class_name(i)
+        if name is None:
+            break
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        code = lib().ptycho_profile_read(i, ctypes.byref(ms), ctypes.byref(n))
+        if code:
+            raise PtychoError(code, "ptycho_profile_read")
+        out[name.decode()] = (ms.value, n.value)
+        i += 1
+    return out
 
 
 def resample_tables(idx, w, device) -> tuple:

@@ -89,6 +89,78 @@ void release_twiddles() {
 
 namespace {
 
+// --------------------------------------------------- per-kernel-class timing
+// Diagnostics only: when enabled, each launch is bracketed by two HIP events
+// recorded on the launch stream; ptycho_profile_read() turns them into
+// total milliseconds per kernel class.
+enum KernelClass {
+  KC_PREP = 0, KC_ROW_FWD, KC_COL_FWD, KC_DET, KC_RESAMPLE, KC_COL_ADJ, KC_PROBE_REDUCE,
+  KC_ROW_ADJ, KC_OBJ_GATHER, KC_FINALIZE, KC_FILL, KC_ADAM, KC_COUNT
+};
+const char* const kClassNames[KC_COUNT] = {
+    "prep", "row_fwd", "col_fwd", "det", "resample", "col_adj", "probe_reduce",
+    "row_adj", "obj_gather", "finalize", "fill", "adam"};
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mutex;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+double g_prof_ms[KC_COUNT];
+long long g_prof_n[KC_COUNT];
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Folds finished records into the totals (caller holds the mutex).
+int prof_collect() {
+  for (auto& r : g_prof_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return PTYCHO_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return PTYCHO_EHIP;
+    g_prof_ms[r.cls] += ms;
+    g_prof_n[r.cls] += 1;
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return PTYCHO_OK;
+}
+
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+    std::lock_guard<std::mutex> lock(g_prof_mutex);
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+  }
+  ~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lock(g_prof_mutex);
+    hipEvent_t b = prof_event();
+    if (b && hipEventRecord(b, s) == hipSuccess) g_prof_recs.push_back({cls, a, b});
+    if (g_prof_recs.size() > 8192) (void)prof_collect();
+  }
+};
+
+}  // namespace
+
+namespace {
+
 bool has_resample(const ptycho_job_t& j) { return j.rs_idx != nullptr; }
 
 int validate_job(const ptycho_job_t& j, bool need_measured) {
@@ -223,6 +295,13 @@ JobDev to_dev(const ptycho_job_t& j) {
     if ((x) != hipSuccess) return PTYCHO_EHIP; \
   } while (0)
 
+// A launch, timed per kernel class when profiling is on.
+#define LAUNCH(cls, x)                         \
+  do {                                         \
+    ProfScope prof_scope_(cls, s);             \
+    if ((x) != hipSuccess) return PTYCHO_EHIP; \
+  } while (0)
+
 int common_checks(const ptycho_job_t* jobs, int n_jobs, bool need_measured) {
   if (!jobs || n_jobs < 1) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i) {
@@ -244,12 +323,12 @@ int run_loss_grad(const ptycho_job_t& job, const ptycho_loss_t& lp, const ptycho
                   int* status, double* loss_k, char* chunk_base, int C, hipStream_t s) {
   JobDev jb = to_dev(job);
   const size_t plane = static_cast<size_t>(job.N) * job.N;
-  if (g.g_object) CHECK_HIP(launch_fill_zero(g.g_object, 2ull * job.L * job.H * job.W, s));
-  if (g.g_probe) CHECK_HIP(launch_fill_zero(g.g_probe, 2ull * job.L * job.M * plane, s));
-  if (g.g_pos) CHECK_HIP(launch_fill_zero(g.g_pos, 2ull * job.K, s));
-  if (g.g_sigma) CHECK_HIP(launch_fill_zero(g.g_sigma, job.K, s));
-  CHECK_HIP(launch_set_status(status, s));
-  CHECK_HIP(launch_validate(jb, status, s));
+  if (g.g_object) LAUNCH(KC_FILL, launch_fill_zero(g.g_object, 2ull * job.L * job.H * job.W, s));
+  if (g.g_probe) LAUNCH(KC_FILL, launch_fill_zero(g.g_probe, 2ull * job.L * job.M * plane, s));
+  if (g.g_pos) LAUNCH(KC_FILL, launch_fill_zero(g.g_pos, 2ull * job.K, s));
+  if (g.g_sigma) LAUNCH(KC_FILL, launch_fill_zero(g.g_sigma, job.K, s));
+  LAUNCH(KC_PREP, launch_set_status(status, s));
+  LAUNCH(KC_PREP, launch_validate(jb, status, s));
   const bool want_grad = g.g_object || g.g_probe || g.g_pos || g.g_sigma;
   LossDev ld{lp.kind, lp.eps, 2.0f * lp.scale};
   for (int k0 = 0; k0 < job.K; k0 += C) {
@@ -258,48 +337,48 @@ int run_loss_grad(const ptycho_job_t& job, const ptycho_loss_t& lp, const ptycho
     w.status = status;
     w.loss_k = loss_k;
     w.k0 = k0;
-    CHECK_HIP(launch_prep(jb, w, s));
-    for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_row_fwd(jb, w, l, s));
-    for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_col_fwd(jb, w, l, s));
+    LAUNCH(KC_PREP, launch_prep(jb, w, s));
+    for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_FWD, launch_row_fwd(jb, w, l, s));
+    for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_FWD, launch_col_fwd(jb, w, l, s));
     int n_loss;
     if (!has_resample(job)) {
-      CHECK_HIP(launch_det(jb, w, ld, want_grad ? 0 : 3, false, nullptr, s));
+      LAUNCH(KC_DET, launch_det(jb, w, ld, want_grad ? 0 : 3, false, nullptr, s));
       n_loss = job.N / rows_per_det_block(job.N);
     } else {
-      CHECK_HIP(launch_det(jb, w, ld, 1, want_grad, w.ibuf, s));
-      CHECK_HIP(launch_resample_loss(jb, w, ld, nullptr, s));
+      LAUNCH(KC_DET, launch_det(jb, w, ld, 1, want_grad, w.ibuf, s));
+      LAUNCH(KC_RESAMPLE, launch_resample_loss(jb, w, ld, nullptr, s));
       n_loss = static_cast<int>((plane + 255) / 256);
       if (want_grad) {
-        CHECK_HIP(launch_resample_T(jb, w, s));
-        CHECK_HIP(launch_det(jb, w, ld, 2, false, nullptr, s));
+        LAUNCH(KC_RESAMPLE, launch_resample_T(jb, w, s));
+        LAUNCH(KC_DET, launch_det(jb, w, ld, 2, false, nullptr, s));
       }
     }
     if (want_grad) {
-      for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_col_adj(jb, w, l, g.g_probe != nullptr, s));
+      for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_ADJ, launch_col_adj(jb, w, l, g.g_probe != nullptr, s));
       if (g.g_probe)
-        CHECK_HIP(launch_probe_reduce(jb, w, reinterpret_cast<float2*>(g.g_probe), s));
+        LAUNCH(KC_PROBE_REDUCE, launch_probe_reduce(jb, w, reinterpret_cast<float2*>(g.g_probe), s));
       if (g.g_object || g.g_pos) {
-        for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_row_adj(jb, w, l, s));
+        for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_ADJ, launch_row_adj(jb, w, l, s));
       }
       if (g.g_object) {
         for (int l = 0; l < job.L; ++l)
-          CHECK_HIP(launch_obj_gather(jb, w, l, reinterpret_cast<float2*>(g.g_object), s));
+          LAUNCH(KC_OBJ_GATHER, launch_obj_gather(jb, w, l, reinterpret_cast<float2*>(g.g_object), s));
       }
     } else {
       // partial buffers of the adjoint are not produced: keep them zero
       const size_t nd = static_cast<size_t>(c) * job.L * (job.N / col_group_of(job.N));
-      CHECK_HIP(launch_fill_zero(w.dy_part, nd, s));
-      CHECK_HIP(launch_fill_zero(w.sg_part, nd, s));
-      CHECK_HIP(launch_fill_zero(w.dx_part,
+      LAUNCH(KC_FILL, launch_fill_zero(w.dy_part, nd, s));
+      LAUNCH(KC_FILL, launch_fill_zero(w.sg_part, nd, s));
+      LAUNCH(KC_FILL, launch_fill_zero(w.dx_part,
                                  static_cast<size_t>(c) * job.L * (job.N / rows_per_adj_block(job.N)), s));
     }
-    CHECK_HIP(launch_finalize_chunk(jb, w, n_loss, g.g_pos, g.g_sigma, s));
+    LAUNCH(KC_FINALIZE, launch_finalize_chunk(jb, w, n_loss, g.g_pos, g.g_sigma, s));
   }
   if (g.loss) {
     Work w{};
     w.status = status;
     w.loss_k = loss_k;
-    CHECK_HIP(launch_loss_total(jb, w, lp.scale, g.loss, s));
+    LAUNCH(KC_FINALIZE, launch_loss_total(jb, w, lp.scale, g.loss, s));
   }
   return PTYCHO_OK;
 }
@@ -345,8 +424,8 @@ int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* i
     const ptycho_job_t& job = jobs[i];
     JobDev jb = to_dev(job);
     int* status = lay.status + i;
-    CHECK_HIP(launch_set_status(status, s));
-    CHECK_HIP(launch_validate(jb, status, s));
+    LAUNCH(KC_PREP, launch_set_status(status, s));
+    LAUNCH(KC_PREP, launch_validate(jb, status, s));
     const size_t plane = static_cast<size_t>(job.N) * job.N;
     for (int k0 = 0; k0 < job.K; k0 += chunks[i]) {
       const int c = std::min(chunks[i], job.K - k0);
@@ -354,16 +433,16 @@ int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* i
       w.status = status;
       w.loss_k = lay.loss_k;
       w.k0 = k0;
-      CHECK_HIP(launch_prep(jb, w, s));
-      for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_row_fwd(jb, w, l, s));
-      for (int l = 0; l < job.L; ++l) CHECK_HIP(launch_col_fwd(jb, w, l, s));
+      LAUNCH(KC_PREP, launch_prep(jb, w, s));
+      for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_FWD, launch_row_fwd(jb, w, l, s));
+      for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_FWD, launch_col_fwd(jb, w, l, s));
       LossDev ld{0, 0.f, 0.f};
       float* out = intensity[i] + static_cast<size_t>(k0) * plane;
       if (!has_resample(job)) {
-        CHECK_HIP(launch_det(jb, w, ld, 1, false, out, s));
+        LAUNCH(KC_DET, launch_det(jb, w, ld, 1, false, out, s));
       } else {
-        CHECK_HIP(launch_det(jb, w, ld, 1, false, w.ibuf, s));
-        CHECK_HIP(launch_resample_loss(jb, w, ld, out, s));
+        LAUNCH(KC_DET, launch_det(jb, w, ld, 1, false, w.ibuf, s));
+        LAUNCH(KC_RESAMPLE, launch_resample_loss(jb, w, ld, out, s));
       }
     }
   }
@@ -415,13 +494,13 @@ int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_
     const float bc2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(a.beta2), a.t)));
     const size_t plane = static_cast<size_t>(j.N) * j.N;
     if (a.lr_object != 0.f)
-      CHECK_HIP(launch_adam(j.object, grads[i].g_object, a.m_object, a.v_object,
+      LAUNCH(KC_ADAM, launch_adam(j.object, grads[i].g_object, a.m_object, a.v_object,
                             2ull * j.L * j.H * j.W, a.lr_object, a.beta1, a.beta2, a.eps, bc1, bc2, s));
     if (a.lr_probe != 0.f)
-      CHECK_HIP(launch_adam(j.probe, grads[i].g_probe, a.m_probe, a.v_probe, 2ull * j.L * j.M * plane,
+      LAUNCH(KC_ADAM, launch_adam(j.probe, grads[i].g_probe, a.m_probe, a.v_probe, 2ull * j.L * j.M * plane,
                             a.lr_probe, a.beta1, a.beta2, a.eps, bc1, bc2, s));
     if (a.lr_pos != 0.f && j.K > 0)
-      CHECK_HIP(launch_adam(j.pos, grads[i].g_pos, a.m_pos, a.v_pos, 2ull * j.K, a.lr_pos, a.beta1,
+      LAUNCH(KC_ADAM, launch_adam(j.pos, grads[i].g_pos, a.m_pos, a.v_pos, 2ull * j.K, a.lr_pos, a.beta1,
                             a.beta2, a.eps, bc1, bc2, s));
   }
   return PTYCHO_OK;
@@ -480,6 +559,39 @@ const char* ptycho_error_string(int32_t code) {
   }
 }
 
-void ptycho_release(void) { release_twiddles(); }
+void ptycho_release(void) {
+  release_twiddles();
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  (void)prof_collect();
+  for (hipEvent_t e : g_prof_pool) (void)hipEventDestroy(e);
+  g_prof_pool.clear();
+}
+
+int32_t ptycho_profile(int32_t enable) {
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  if (prof_collect() != PTYCHO_OK) return PTYCHO_EHIP;
+  if (enable) {
+    for (int i = 0; i < KC_COUNT; ++i) {
+      g_prof_ms[i] = 0.0;
+      g_prof_n[i] = 0;
+    }
+  }
+  g_prof_on = enable != 0;
+  return PTYCHO_OK;
+}
+
+int32_t ptycho_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches) {
+  if (kernel_class < 0 || kernel_class >= KC_COUNT || !total_ms || !launches) return PTYCHO_EINVAL;
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  if (prof_collect() != PTYCHO_OK) return PTYCHO_EHIP;
+  *total_ms = g_prof_ms[kernel_class];
+  *launches = g_prof_n[kernel_class];
+  return PTYCHO_OK;
+}
+
+const char* ptycho_kernel_class_name(int32_t kernel_class) {
+  if (kernel_class < 0 || kernel_class >= KC_COUNT) return nullptr;
+  return kClassNames[kernel_class];
+}
 
 }  // extern "C"
