@@ -1,0 +1,121 @@
+"""torch.autograd.Function wrappers around the C ABI.
+
+``PtychoLoss`` returns the scalar loss of Eq. 1's model against the measured
+patterns; its backward multiplies the library's hand-written gradients
+(object, probe, positions, power coefficients) by the incoming gradient.
+The forward call already computes the gradients (one fused pass), so the
+backward is a scaling only.
+
+``PtychoForward`` returns the predicted patterns I'_k; its backward is the
+vector-Jacobian product, computed by the same library call with the VJP loss
+kind (the upstream gradient takes the place of the measured patterns).
+
+Complex gradients follow PyTorch's convention for real-valued losses,
+G = dL/dRe + i dL/dIm, which is also the library's.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import binding as B
+
+
+def _zeros_like_grads(problem: B.Problem, need):
+    dev = problem.object.device
+    g = dict(loss=torch.zeros(1, device=dev))
+    if need[0]:
+        g["g_object"] = torch.zeros_like(problem.object)
+    if need[1]:
+        g["g_probe"] = torch.zeros_like(problem.probe)
+    if need[2]:
+        g["g_pos"] = torch.zeros(problem.K, 2, device=dev)
+    if need[3]:
+        g["g_sigma"] = torch.zeros(problem.K, device=dev)
+    return g
+
+
+class _Workspace:
+    """Caches one device workspace per (device, size)."""
+
+    def __init__(self):
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, problem: B.Problem, which: int, chunk: int = 0) -> torch.Tensor:
+        n = B.ptycho_workspace_bytes([problem], which, chunk)
+        if self.buf is None or self.buf.numel() < n or self.buf.device != problem.object.device:
+            self.buf = torch.empty(n, dtype=torch.uint8, device=problem.object.device)
+        return self.buf
+
+
+_WS = _Workspace()
+
+
+class PtychoLossFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, obj, probe, pos, sigma, pads, measured, background, mask, resample,
+                kind, eps, scale, chunk):
+        prob = B.Problem(object=obj.detach().contiguous(), probe=probe.detach().contiguous(),
+                         pos=pos.detach().contiguous(), pads=tuple(pads),
+                         measured=measured.contiguous(),
+                         sigma=None if sigma is None else sigma.detach().contiguous(),
+                         background=background, mask=mask, resample=resample)
+        need = tuple(ctx.needs_input_grad[:3]) + (sigma is not None and ctx.needs_input_grad[3],)
+        g = _zeros_like_grads(prob, need)
+        ws = _WS.get(prob, 1, chunk)
+        B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws)
+        ctx.save_for_backward(*(g.get(k) for k in ("g_object", "g_probe", "g_pos", "g_sigma")
+                                if g.get(k) is not None))
+        ctx.have = tuple(g.get(k) is not None for k in ("g_object", "g_probe", "g_pos", "g_sigma"))
+        return g["loss"][0]
+
+    @staticmethod
+    def backward(ctx, gout):
+        saved = list(ctx.saved_tensors)
+        out = []
+        for have in ctx.have:
+            out.append(saved.pop(0) * gout if have else None)
+        return (out[0], out[1], out[2], out[3]) + (None,) * 9
+
+
+def ptycho_loss(obj, probe, pos, pads, measured, sigma=None, background=None, mask=None,
+                resample=None, kind: int = B.LOSS_AMPLITUDE, eps: float = 1e-6,
+                scale: float = 1.0, chunk: int = 0) -> torch.Tensor:
+    """Scalar loss (differentiable w.r.t. obj, probe, pos and sigma)."""
+    return PtychoLossFn.apply(obj, probe, pos, sigma, tuple(pads), measured, background, mask,
+                              resample, int(kind), float(eps), float(scale), int(chunk))
+
+
+class PtychoForwardFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, obj, probe, pos, sigma, pads, background, mask, resample, chunk):
+        prob = B.Problem(object=obj.detach().contiguous(), probe=probe.detach().contiguous(),
+                         pos=pos.detach().contiguous(), pads=tuple(pads),
+                         sigma=None if sigma is None else sigma.detach().contiguous(),
+                         background=background, mask=mask, resample=resample)
+        out = torch.empty(prob.K, prob.N, prob.N, device=obj.device)
+        ws = _WS.get(prob, 0, chunk)
+        B.ptycho_forward([prob], [out], ws)
+        ctx.prob = prob
+        ctx.chunk = chunk
+        ctx.need = tuple(ctx.needs_input_grad[:3]) + (sigma is not None and ctx.needs_input_grad[3],)
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        prob = ctx.prob
+        prob.measured = gout.contiguous().float()
+        g = _zeros_like_grads(prob, ctx.need)
+        ws = _WS.get(prob, 1, ctx.chunk)
+        B.ptycho_loss_grad([prob], [g], kind=B.LOSS_VJP, eps=0.0, scale=1.0, workspace=ws)
+        prob.measured = None
+        return (g.get("g_object"), g.get("g_probe"), g.get("g_pos"), g.get("g_sigma"),
+                None, None, None, None, None)
+
+
+def ptycho_forward(obj, probe, pos, pads, sigma=None, background=None, mask=None, resample=None,
+                   chunk: int = 0) -> torch.Tensor:
+    """Predicted patterns I'_k [K][N][N] (differentiable)."""
+    return PtychoForwardFn.apply(obj, probe, pos, sigma, tuple(pads), background, mask, resample,
+                                 int(chunk))

@@ -46,10 +46,21 @@ int init_twiddles() {
   DeviceTables t;
   for (int n : kLengths) {
     t.offset[n] = host.size();
-    for (int i = 0; i < n; ++i) {
-      // T_n[i] = exp(-2 pi i i / n), evaluated in float64, rounded to float32
-      const double a = 2.0 * M_PI * static_cast<double>(i) / static_cast<double>(n);
-      host.push_back(make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a))));
+    int rad[16];
+    const int np = plan_radices(n, rad);
+    if (np < 1) return PTYCHO_EHIP;
+    // per pass p > 0: [k][r - 1] = exp(-2 pi i r k / (Ns R)), k < Ns, 1 <= r < R,
+    // evaluated in float64 and rounded to float32
+    int Ns = rad[0];
+    for (int p = 1; p < np; ++p) {
+      const int R = rad[p];
+      for (int k = 0; k < Ns; ++k) {
+        for (int r = 1; r < R; ++r) {
+          const double a = 2.0 * M_PI * static_cast<double>(r * k) / static_cast<double>(Ns * R);
+          host.push_back(make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a))));
+        }
+      }
+      Ns *= R;
     }
     while (host.size() % 32) host.push_back(make_float2(0.f, 0.f));
   }

@@ -20,6 +20,32 @@
 
 namespace ptycho {
 
+// Address-space qualified pointers for out-of-line device functions, whose
+// generic pointer arguments would otherwise be accessed with flat
+// instructions (flat loads also hold the LDS wait counter).
+// Complex values behind such pointers use the native two-float vector type.
+#define PTYCHO_GLOBAL __attribute__((address_space(1)))
+#define PTYCHO_LDS __attribute__((address_space(3)))
+using vf2 = float __attribute__((ext_vector_type(2)));
+using gf2 = PTYCHO_GLOBAL vf2;
+using lf2 = PTYCHO_LDS vf2;
+using lf32 = PTYCHO_LDS float;
+
+// Element access that works for generic float2 pointers and for the
+// address-space qualified vector pointers above.
+__device__ __forceinline__ float2 ldv(const float2* p, int i) { return p[i]; }
+__device__ __forceinline__ float2 ldv(const lf2* p, int i) {
+  const vf2 t = p[i];
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ float2 ldv(const gf2* p, int i) {
+  const vf2 t = p[i];
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ void stv(float2* p, int i, float2 v) { p[i] = v; }
+__device__ __forceinline__ void stv(lf2* p, int i, float2 v) { p[i] = vf2{v.x, v.y}; }
+__device__ __forceinline__ void stv(gf2* p, int i, float2 v) { p[i] = vf2{v.x, v.y}; }
+
 // ----------------------------------------------------------- complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -229,59 +255,105 @@ struct Plan;  // Plan<n>::type = Radices<...>, product n
     using type = Radices<__VA_ARGS__>; \
   };
 
+// Lengths that are multiples of 16 use the skewed row layout (see Lds) and
+// power-of-two radices first; the others start with an odd radix, so that the
+// strided writes of the first pass do not pile onto a few LDS banks.
 PTYCHO_PLAN(64, 8, 8)
-PTYCHO_PLAN(72, 8, 9)
+PTYCHO_PLAN(72, 9, 8)
 PTYCHO_PLAN(80, 16, 5)
-PTYCHO_PLAN(84, 12, 7)
+PTYCHO_PLAN(84, 7, 12)
 PTYCHO_PLAN(90, 9, 10)
 PTYCHO_PLAN(96, 8, 12)
 PTYCHO_PLAN(128, 16, 8)
-PTYCHO_PLAN(140, 10, 14)
-PTYCHO_PLAN(150, 10, 15)
-PTYCHO_PLAN(168, 12, 14)
+PTYCHO_PLAN(140, 7, 5, 4)
+PTYCHO_PLAN(150, 15, 10)
+PTYCHO_PLAN(168, 7, 3, 8)
 PTYCHO_PLAN(189, 7, 3, 9)
 PTYCHO_PLAN(256, 16, 16)
-PTYCHO_PLAN(280, 8, 5, 7)
-PTYCHO_PLAN(300, 12, 5, 5)
-PTYCHO_PLAN(315, 9, 5, 7)
+PTYCHO_PLAN(280, 7, 5, 8)
+PTYCHO_PLAN(300, 5, 5, 12)
+PTYCHO_PLAN(315, 7, 5, 9)
 PTYCHO_PLAN(336, 16, 3, 7)
 PTYCHO_PLAN(343, 7, 7, 7)
 PTYCHO_PLAN(375, 15, 5, 5)
 PTYCHO_PLAN(384, 16, 8, 3)
-PTYCHO_PLAN(420, 12, 5, 7)
+PTYCHO_PLAN(420, 7, 5, 12)
 PTYCHO_PLAN(480, 16, 6, 5)
 PTYCHO_PLAN(512, 8, 8, 8)
 PTYCHO_PLAN(560, 16, 5, 7)
-PTYCHO_PLAN(600, 12, 10, 5)
+PTYCHO_PLAN(600, 5, 12, 10)
 PTYCHO_PLAN(675, 9, 15, 5)
-PTYCHO_PLAN(750, 10, 15, 5)
+PTYCHO_PLAN(750, 5, 15, 10)
 #undef PTYCHO_PLAN
+
+// Radices of a plan as a host/device array (for building twiddle tables).
+template <int... Rs>
+constexpr int plan_count(Radices<Rs...>) { return sizeof...(Rs); }
+template <int n>
+struct PlanInfo {
+  static constexpr int passes = plan_count(typename Plan<n>::type{});
+};
+template <int... Rs>
+inline void plan_fill(Radices<Rs...>, int* out) {
+  const int r[] = {Rs...};
+  for (int i = 0; i < static_cast<int>(sizeof...(Rs)); ++i) out[i] = r[i];
+}
 
 // ------------------------------------------------------ the Stockham engine
 // Layout of element i of line `line` in the LDS buffer.
 //  LINE_FAST = true : buf[i * LP + line]  (column groups: lanes walk lines;
 //                     LP = lines + 1)
-//  LINE_FAST = false: buf[line * LP + i + i / 16]  (rows: lanes walk elements;
-//                     one skew word per 16 keeps radix-16 strided writes
-//                     spread over the LDS banks; LP >= row_lp(n))
-template <int LINES, int LP, bool LINE_FAST>
+//  LINE_FAST = false: buf[line * LP + i (+ i / 16 if n % 16 == 0)]  (rows:
+//                     lanes walk elements; for lengths that are multiples of
+//                     16 one skew word per 16 elements keeps the power-of-two
+//                     strided writes spread over the LDS banks).
+template <int n>
+constexpr bool row_skew() { return n % 16 == 0; }
+constexpr int row_lp(int n) { return n % 16 == 0 ? n + (n >> 4) + 1 : n + 1; }
+
+template <int n, int LP, bool LINE_FAST>
 struct Lds {
   __device__ __forceinline__ static int at(int line, int i) {
-    return LINE_FAST ? i * LP + line : line * LP + i + (i >> 4);
+    if (LINE_FAST) return i * LP + line;
+    return row_skew<n>() ? line * LP + i + (i >> 4) : line * LP + i;
+  }
+  // Address of element base + r * STRIDE, r a compile-time loop index.  When
+  // the skew of the element is known up to a constant per r it is folded into
+  // an immediate offset from the address of `base`:
+  //  MODE 1: the R elements lie in one aligned 16-element block (same skew);
+  //  MODE 2: base < STRIDE and STRIDE divides 16 (skew = (r STRIDE) / 16);
+  //  MODE 0: anything else, computed per element.
+  template <int STRIDE, int MODE>
+  __device__ __forceinline__ static int at_r(int line, int base, int r) {
+    if (LINE_FAST) return at(line, base) + r * STRIDE * LP;
+    if (!row_skew<n>()) return at(line, base) + r * STRIDE;
+    if (STRIDE % 16 == 0) return at(line, base) + r * (STRIDE + STRIDE / 16);
+    if (MODE == 1) return at(line, base) + r * STRIDE;
+    if (MODE == 2) return at(line, base) + r * STRIDE + ((r * STRIDE) >> 4);
+    return at(line, base + r * STRIDE);
   }
 };
-constexpr int row_lp(int n) { return n + (n >> 4) + 1; }
+
+// Twiddle table of length n (host-built, float64 -> float32): for every pass
+// p > 0 with radix R and Ns = product of earlier radices, Ns * (R - 1)
+// entries w_{Ns R}^{r k} (forward sign) stored as [k][r - 1], k < Ns,
+// 1 <= r < R; passes are concatenated in plan order.
 
 // One Stockham pass.  FIRST: inputs from `load(line, i)`; otherwise from LDS.
-// LAST: outputs to `store(line, i, v)`; otherwise to LDS.
-template <int n, int R, int Ns, bool FIRST, bool LAST, bool INV, int LINES, int NT, int LP,
-          bool LINE_FAST, class Load, class Store>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw,
-                                              const Load& load, const Store& store) {
+// LAST: outputs to `store(line, i, v)`; otherwise to LDS.  TOFF: offset of
+// this pass's twiddles in the table.
+template <int n, int R, int Ns, int TOFF, bool FIRST, bool LAST, bool INV, int LINES, int NT,
+          int LP, bool LINE_FAST, class Buf, class Tw, class Load, class Store>
+__device__ __forceinline__ void stockham_pass(Buf buf, Tw tw, const Load& load, const Store& store) {
   constexpr int NB = n / R;             // butterflies per line
   constexpr int BF = LINES * NB;        // butterflies per pass
   constexpr int ITER = (BF + NT - 1) / NT;
-  using Ix = Lds<LINES, LP, LINE_FAST>;
+  using Ix = Lds<n, LP, LINE_FAST>;
+  // reads: i = j + r NB with j < NB
+  constexpr int RD_MODE = (16 % NB == 0) ? 2 : 0;
+  // writes: o = base + r Ns, base = (j / Ns) Ns R + j % Ns; all o of a
+  // butterfly lie in one aligned block of Ns R elements
+  constexpr int WR_MODE = (16 % (Ns * R) == 0) ? 1 : 0;
   const int tid = threadIdx.x;
   float2 v[ITER][R];
 #pragma unroll
@@ -290,19 +362,26 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
     if ((BF % NT == 0) || b < BF) {
       const int line = LINE_FAST ? (b % LINES) : (b / NB);
       const int j = LINE_FAST ? (b / LINES) : (b % NB);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = j + r * NB;
-        v[it][r] = FIRST ? load(line, i) : buf[Ix::at(line, i)];
-      }
       if (Ns > 1) {
+        // issue the twiddle loads first: one address, constant offsets
         const int k = j % Ns;
+        const auto t = tw + TOFF + k * (R - 1);
+        float2 w[R - 1];
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r - 1] = ldv(t, r - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * (n / (Ns * R))];
-          if (INV) w.y = -w.y;
-          v[it][r] = cmul(v[it][r], w);
+          float2 ww = w[r - 1];
+          if (INV) ww.y = -ww.y;
+          v[it][r] = cmul(v[it][r], ww);
         }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
       }
       Dft<R, INV>::run(v[it]);
     }
@@ -317,38 +396,37 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
       const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int o = base + r * Ns;
         if (LAST)
-          store(line, o, v[it][r]);
+          store(line, base + r * Ns, v[it][r]);
         else
-          buf[Ix::at(line, o)] = v[it][r];
+          stv(buf, Ix::template at_r<Ns, WR_MODE>(line, base, r), v[it][r]);
       }
     }
   }
   __syncthreads();
 }
 
-template <int n, int Ns, bool FIRST, bool INV, int LINES, int NT, int LP, bool LINE_FAST,
-          class Load, class Store, int R, int... Rest>
-__device__ __forceinline__ void stockham_run(float2* buf, const float2* __restrict__ tw,
-                                             const Load& load, const Store& store,
+template <int n, int Ns, int TOFF, bool FIRST, bool INV, int LINES, int NT, int LP, bool LINE_FAST,
+          class Buf, class Tw, class Load, class Store, int R, int... Rest>
+__device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const Load& load, const Store& store,
                                              Radices<R, Rest...>) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  stockham_pass<n, R, Ns, FIRST, LAST, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store);
+  stockham_pass<n, R, Ns, TOFF, FIRST, LAST, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store);
   if constexpr (!LAST) {
-    stockham_run<n, Ns * R, false, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
-                                                                   Radices<Rest...>{});
+    constexpr int NEXT_TOFF = TOFF + (Ns > 1 ? Ns * (R - 1) : 0);
+    stockham_run<n, Ns * R, NEXT_TOFF, false, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
+                                                                              Radices<Rest...>{});
   }
 }
 
 // Full FFT of LINES lines of length n: inputs via load(line, i) (i in [0, n)),
-// outputs via store(line, i, value).  `buf` must hold LINES * n elements laid
-// out as Lds<LINES, LP, LINE_FAST>.  The call begins with the first pass's
-// reads (the caller must have synchronised any earlier use of `buf`) and ends
-// with a workgroup barrier.  Unnormalised in both directions.
-template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Load, class Store>
-__device__ __forceinline__ void fft_lines(float2* buf, const float2* __restrict__ tw,
-                                          const Load& load, const Store& store) {
+// outputs via store(line, i, value).  `buf` must hold LINES lines laid out as
+// Lds<n, LP, LINE_FAST>.  The call begins with the first pass's reads (the
+// caller must have synchronised any earlier use of `buf`) and ends with a
+// workgroup barrier.  Unnormalised in both directions.
+template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Buf, class Tw,
+          class Load, class Store>
+__device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, const Store& store) {
   // The twiddle base is made opaque here so that the compiler cannot hoist
   // the (loop-invariant) twiddle loads of an FFT out of an enclosing loop,
   // which would pin every twiddle value in registers for the whole loop.
@@ -357,10 +435,10 @@ __device__ __forceinline__ void fft_lines(float2* buf, const float2* __restrict_
     unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
     unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
-    tw = reinterpret_cast<const float2*>((static_cast<unsigned long long>(hi) << 32) | lo);
+    tw = reinterpret_cast<Tw>((static_cast<unsigned long long>(hi) << 32) | lo);
   }
-  stockham_run<n, 1, true, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
-                                                           typename Plan<n>::type{});
+  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
+                                                              typename Plan<n>::type{});
 }
 
 }  // namespace ptycho

@@ -33,6 +33,12 @@ constexpr int kERange = -2;
 
 template <int... Ps>
 struct IntList {};
+template <int... Ps>
+constexpr int max_row_lp(IntList<Ps...>) {
+  int m = 0;
+  for (int p : {Ps...}) m = row_lp(p) > m ? row_lp(p) : m;
+  return m;
+}
 
 // DFT sizes compiled in, per window size N.
 template <int N>
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(JobDev jb, Work w, int l) {
   if (*w.status) return;
   constexpr int RB = rb_row<N>();
   constexpr int LP = row_lp(N);
-  using Ix = Lds<RB, LP, false>;
+  using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[RB * LP];
   const int c = blockIdx.y, k = w.k0 + c;
   const int y0 = blockIdx.x * RB;
@@ -232,16 +238,16 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(JobDev jb, Work w, int l) {
 // Kept out of line so that each DFT size gets its own register allocation
 // inside the kernel's run-time switch over the wavelengths' pad sizes.
 template <int N, int NL, int RB>
-__device__ __noinline__ void det_rows_fwd(float2* buf, float* acc, float2* __restrict__ Yr,
-                                          const float2* __restrict__ twL, float ps, bool keep) {
+__device__ __noinline__ void det_rows_fwd(lf2* buf, lf32* acc, gf2* __restrict__ Yr,
+                                          const gf2* __restrict__ twL, float ps, bool keep) {
   constexpr int LP = row_lp(NL);
-  auto ld = [&](int line, int t) { return t < N ? Yr[line * N + t] : make_float2(0.f, 0.f); };
+  auto ld = [&](int line, int t) { return t < N ? ldv(Yr, line * N + t) : make_float2(0.f, 0.f); };
   auto st = [&](int line, int t, float2 v) {
     int u = t + N / 2;
     if (u >= NL) u -= NL;
     if (u < N) {
       v = cscale(v, ps);
-      if (keep) Yr[line * N + u] = v;
+      if (keep) stv(Yr, line * N + u, v);
       acc[line * N + u] += cabs2(v);
     }
   };
@@ -251,16 +257,16 @@ __device__ __noinline__ void det_rows_fwd(float2* buf, float* acc, float2* __res
 // Adjoint row pass: Z[u][:] = (1/sqrt(NL)) DFT^H_NL_x( embed( g2 Psi[u][:] ) )[0:N],
 // g2 = acc (2 scale w dloss/dI), written over Psi.
 template <int N, int NL, int RB>
-__device__ __noinline__ void det_rows_adj(float2* buf, const float* acc, float2* __restrict__ Yr,
-                                          const float2* __restrict__ twL, float ps) {
+__device__ __noinline__ void det_rows_adj(lf2* buf, const lf32* acc, gf2* __restrict__ Yr,
+                                          const gf2* __restrict__ twL, float ps) {
   constexpr int LP = row_lp(NL);
   auto ld = [&](int line, int t) {
     int u = t + N / 2;
     if (u >= NL) u -= NL;
-    return u < N ? cscale(Yr[line * N + u], acc[line * N + u]) : make_float2(0.f, 0.f);
+    return u < N ? cscale(ldv(Yr, line * N + u), acc[line * N + u]) : make_float2(0.f, 0.f);
   };
   auto st = [&](int line, int t, float2 v) {
-    if (t < N) Yr[line * N + t] = cscale(v, ps);
+    if (t < N) stv(Yr, line * N + t, cscale(v, ps));
   };
   fft_lines<NL, true, RB, NT, LP, false>(buf, twL, ld, st);
 }
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
                                             float* __restrict__ out) {
   if (*w.status) return;
   constexpr int RB = rb_det<N>();
-  constexpr int LPMAX = row_lp(PadList<N>::max);
+  constexpr int LPMAX = max_row_lp(typename PadList<N>::type{});
   __shared__ float2 buf[RB * LPMAX];
   __shared__ float acc[RB * N];
   __shared__ float red[NT / 64];
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
                      static_cast<size_t>(u0) * N;
         pad_switch(nl, [&](auto nlc) {
           constexpr int NL = decltype(nlc)::value;
-          det_rows_fwd<N, NL, RB>(buf, acc, Yr, twL, ps, keep);
+          det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, (gf2*)Yr, (const gf2*)twL, ps, keep);
         }, typename PadList<N>::type{});
       }
     }
@@ -350,7 +356,7 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
                    static_cast<size_t>(u0) * N;
       pad_switch(nl, [&](auto nlc) {
         constexpr int NL = decltype(nlc)::value;
-        det_rows_adj<N, NL, RB>(buf, acc, Yr, twL, ps);
+        det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, (gf2*)Yr, (const gf2*)twL, ps);
       }, typename PadList<N>::type{});
     }
   }
@@ -544,8 +550,8 @@ __global__ __launch_bounds__(NT) void k_row_adj(JobDev jb, Work w, int l) {
   if (*w.status) return;
   constexpr int RB = rb_adj<N>();
   constexpr int LP = row_lp(N);
-  using Ix2 = Lds<2 * RB, LP, false>;
-  using Ix1 = Lds<RB, LP, false>;
+  using Ix2 = Lds<N, LP, false>;
+  using Ix1 = Lds<N, LP, false>;
   __shared__ float2 buf[2 * RB * LP];
   __shared__ float red[NT / 64];
   const int c = blockIdx.y, y0 = blockIdx.x * RB;
@@ -707,6 +713,24 @@ inline unsigned blocks_for(size_t n, unsigned per) {
 }
 
 }  // namespace
+
+namespace {
+template <int P, int... Ps>
+int plan_of(int n, int* out, IntList<P, Ps...>) {
+  if (n == P) {
+    plan_fill(typename Plan<P>::type{}, out);
+    return PlanInfo<P>::passes;
+  }
+  if constexpr (sizeof...(Ps) > 0) return plan_of(n, out, IntList<Ps...>{});
+  return 0;
+}
+}  // namespace
+
+int plan_radices(int n, int* out) {
+  using All = IntList<64, 72, 80, 84, 90, 96, 128, 140, 150, 168, 189, 256, 280, 300, 315, 336,
+                      343, 375, 384, 420, 480, 512, 560, 600, 675, 750>;
+  return plan_of(n, out, All{});
+}
 
 bool supported(int N, int nl) {
   switch (N) {

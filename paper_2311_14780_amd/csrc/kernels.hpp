@@ -54,7 +54,10 @@ struct Work {
   int k0, C;
 };
 
-// Twiddle table lookup: T_n[t] = exp(-2 pi i t / n), t < n, on this device.
+// Radix plan of an FFT length (returns the number of passes, 0 if unknown).
+int plan_radices(int n, int* out);
+
+// Per-pass twiddle table of length n on this device (layout in fft.hpp).
 const float2* twiddles(int n);
 int init_twiddles();  // returns 0 or a PTYCHO_E* code
 void release_twiddles();
