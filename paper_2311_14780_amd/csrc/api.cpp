@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <vector>
 
@@ -106,11 +107,11 @@ namespace {
 // total milliseconds per kernel class.
 enum KernelClass {
   KC_PREP = 0, KC_ROW_FWD, KC_COL_FWD, KC_DET, KC_RESAMPLE, KC_COL_ADJ, KC_PROBE_REDUCE,
-  KC_ROW_ADJ, KC_OBJ_GATHER, KC_FINALIZE, KC_FILL, KC_ADAM, KC_COUNT
+  KC_ROW_ADJ, KC_OBJ_GATHER, KC_FINALIZE, KC_FILL, KC_ADAM, KC_TABLES, KC_COUNT
 };
 const char* const kClassNames[KC_COUNT] = {
     "prep", "row_fwd", "col_fwd", "det", "resample", "col_adj", "probe_reduce",
-    "row_adj", "obj_gather", "finalize", "fill", "adam"};
+    "row_adj", "obj_gather", "finalize", "fill", "adam", "tables"};
 
 struct ProfRec {
   int cls;
@@ -196,18 +197,22 @@ int validate_job(const ptycho_job_t& j, bool need_measured) {
   return PTYCHO_OK;
 }
 
+int n_loss_of(const ptycho_job_t& j) {
+  const int plane = j.N * j.N;
+  return has_resample(j) ? (plane + 255) / 256 : j.N / rows_per_det_block(j.N);
+}
+
 // Bytes of workspace that scale with the number of positions in a chunk.
 size_t per_position_bytes(const ptycho_job_t& j, int which) {
   const size_t N = j.N, L = j.L, M = j.M;
   const size_t plane = N * N;
   size_t b = 0;
-  b += align_up(2 * N * sizeof(float2));      // ramp
-  b += align_up(L * plane * sizeof(float2));  // X
+  b += align_up(2 * N * sizeof(float2));          // ramp
+  b += align_up(L * plane * sizeof(float2));      // X
   b += align_up(L * M * plane * sizeof(float2));  // Y
   if (which != 0) {
     b += align_up(L * plane * sizeof(float2));  // GX
-    const size_t nloss = std::max<size_t>(N / rows_per_det_block(j.N), (plane + 255) / 256);
-    b += align_up(nloss * sizeof(float));
+    b += align_up(static_cast<size_t>(n_loss_of(j)) * sizeof(float));
     b += 2 * align_up(L * (N / col_group_of(j.N)) * sizeof(float));  // dy, sigma
     b += align_up(L * (N / rows_per_adj_block(j.N)) * sizeof(float));  // dx
   }
@@ -215,64 +220,119 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
   return b;
 }
 
+constexpr int kSegsPerJob = 72;  // bound on the segments one job adds to one phase
+
 size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
-  size_t kmax = 0;
-  for (int i = 0; i < n_jobs; ++i) kmax = std::max<size_t>(kmax, jobs[i].K);
-  return align_up(sizeof(int) * n_jobs) + align_up(std::max<size_t>(kmax, 1) * sizeof(double));
+  size_t b = align_up(sizeof(int) * n_jobs);                        // status
+  b += align_up(sizeof(JobDev) * n_jobs);                           // job table
+  b += align_up(sizeof(Seg) * static_cast<size_t>(kSegsPerJob) * n_jobs);  // segment pool
+  for (int i = 0; i < n_jobs; ++i) b += align_up(std::max<size_t>(jobs[i].K, 1) * sizeof(double));
+  return b;
 }
 
-struct Layout {
-  int* status;
-  double* loss_k;
-  char* chunk_base;
-  size_t chunk_bytes;
+// Key of a launch group: jobs of one group share every kernel instance.
+struct GroupKey {
+  int N;
+  bool resample;
+  bool adjoint;
+  bool operator<(const GroupKey& o) const {
+    return std::tie(N, resample, adjoint) < std::tie(o.N, o.resample, o.adjoint);
+  }
 };
 
-Layout make_layout(void* ws, size_t ws_bytes, const ptycho_job_t* jobs, int n_jobs) {
-  Layout lay;
+// Host view of one call.
+struct Call {
+  int which;  // 0 forward, 1 loss + gradient, 2 step
+  int n;
+  const ptycho_job_t* jobs;
+  const ptycho_grads_t* grads;  // [n] or null (forward)
+  const ptycho_adam_t* adam;    // [n] or null
+  float* const* out;            // [n] or null
+  LossDev loss{};
+  float scale = 1.f;
+  // workspace
+  int* status = nullptr;
+  JobDev* jobs_dev = nullptr;
+  Seg* seg_pool = nullptr;
+  std::vector<double*> loss_k;
+  char* chunk_base = nullptr;
+  size_t chunk_bytes = 0;
+  std::vector<JobDev> host_jobs;
+  std::vector<int> chunk;  // C per job
+};
+
+bool wants_adjoint(const Call& c, int i) {
+  if (c.which == 0) return false;
+  const ptycho_grads_t& g = c.grads[i];
+  return g.g_object || g.g_probe || g.g_pos || g.g_sigma;
+}
+
+int layout(Call& c, void* ws, size_t ws_bytes) {
   char* p = static_cast<char*>(ws);
-  lay.status = reinterpret_cast<int*>(p);
-  p += align_up(sizeof(int) * n_jobs);
-  size_t kmax = 0;
-  for (int i = 0; i < n_jobs; ++i) kmax = std::max<size_t>(kmax, jobs[i].K);
-  lay.loss_k = reinterpret_cast<double*>(p);
-  p += align_up(std::max<size_t>(kmax, 1) * sizeof(double));
-  lay.chunk_base = p;
-  const size_t used = static_cast<size_t>(p - static_cast<char*>(ws));
-  lay.chunk_bytes = ws_bytes > used ? ws_bytes - used : 0;
-  return lay;
+  char* end = p + ws_bytes;
+  c.status = reinterpret_cast<int*>(p);
+  p += align_up(sizeof(int) * c.n);
+  c.jobs_dev = reinterpret_cast<JobDev*>(p);
+  p += align_up(sizeof(JobDev) * c.n);
+  c.seg_pool = reinterpret_cast<Seg*>(p);
+  p += align_up(sizeof(Seg) * static_cast<size_t>(kSegsPerJob) * c.n);
+  c.loss_k.resize(c.n);
+  for (int i = 0; i < c.n; ++i) {
+    c.loss_k[i] = reinterpret_cast<double*>(p);
+    p += align_up(std::max<size_t>(c.jobs[i].K, 1) * sizeof(double));
+  }
+  if (p > end) return PTYCHO_ENOSPC;
+  c.chunk_base = p;
+  c.chunk_bytes = static_cast<size_t>(end - p);
+  return PTYCHO_OK;
 }
 
-Work chunk_views(const ptycho_job_t& j, int which, char* base, int C) {
-  const size_t N = j.N, L = j.L, M = j.M, plane = N * N;
-  Work w{};
-  char* p = base;
-  auto take = [&](size_t bytes) {
-    char* r = p;
-    p += align_up(bytes);
-    return r;
+// Chunk sizes of the jobs of one group: the fewest iterations T such that
+// the group's per-chunk workspaces fit; C_j = ceil(K_j / T).
+int plan_chunks(Call& c, const std::vector<int>& members, int* iters) {
+  int kmax = 0;
+  for (int i : members) kmax = std::max(kmax, c.jobs[i].K);
+  if (kmax == 0) {
+    for (int i : members) c.chunk[i] = 1;
+    *iters = 0;
+    return PTYCHO_OK;
+  }
+  const int w = c.which == 0 ? 0 : 1;
+  auto need = [&](int T) {
+    size_t b = 0;
+    for (int i : members) {
+      const int K = c.jobs[i].K;
+      if (K == 0) continue;
+      b += per_position_bytes(c.jobs[i], w) * static_cast<size_t>((K + T - 1) / T);
+    }
+    return b;
   };
-  w.ramp = reinterpret_cast<float2*>(take(C * 2 * N * sizeof(float2)));
-  w.X = reinterpret_cast<float2*>(take(C * L * plane * sizeof(float2)));
-  w.Y = reinterpret_cast<float2*>(take(C * L * M * plane * sizeof(float2)));
-  if (which != 0) {
-    w.GX = reinterpret_cast<float2*>(take(C * L * plane * sizeof(float2)));
-    const size_t nloss = std::max<size_t>(N / rows_per_det_block(j.N), (plane + 255) / 256);
-    w.loss_part = reinterpret_cast<float*>(take(C * nloss * sizeof(float)));
-    w.dy_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
-    w.sg_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
-    w.dx_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_adj_block(j.N)) * sizeof(float)));
+  if (need(kmax) > c.chunk_bytes) return PTYCHO_ENOSPC;
+  int lo = 1, hi = kmax;  // smallest T with need(T) <= chunk_bytes
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (need(mid) <= c.chunk_bytes) hi = mid; else lo = mid + 1;
   }
-  if (has_resample(j)) {
-    w.ibuf = reinterpret_cast<float*>(take(C * plane * sizeof(float)));
-    w.gbuf = reinterpret_cast<float*>(take(C * plane * sizeof(float)));
+  int T = lo;
+  for (int i : members) {
+    const int K = c.jobs[i].K;
+    c.chunk[i] = K == 0 ? 1 : (K + T - 1) / T;
   }
-  w.C = C;
-  return w;
+  // iterations actually needed with these chunk sizes
+  int it = 0;
+  for (int i : members) {
+    const int K = c.jobs[i].K;
+    if (K) it = std::max(it, (K + c.chunk[i] - 1) / c.chunk[i]);
+  }
+  *iters = it;
+  return PTYCHO_OK;
 }
 
-JobDev to_dev(const ptycho_job_t& j) {
-  JobDev d{};
+// Fill the device view of job i, its workspace starting at *cursor.
+void fill_job(Call& c, int i, char** cursor) {
+  const ptycho_job_t& j = c.jobs[i];
+  JobDev& d = c.host_jobs[i];
+  d = JobDev{};
   d.object = reinterpret_cast<const float2*>(j.object);
   d.probe = reinterpret_cast<const float2*>(j.probe);
   d.pos = j.pos;
@@ -298,11 +358,89 @@ JobDev to_dev(const ptycho_job_t& j) {
     d.pad_scale[l] = static_cast<float>(1.0 / std::sqrt(static_cast<double>(nl)));
     d.tw_pad[l] = twiddles(nl);
   }
-  return d;
+  if (c.grads) {
+    const ptycho_grads_t& g = c.grads[i];
+    d.loss = g.loss;
+    d.g_object = reinterpret_cast<float2*>(g.g_object);
+    d.g_probe = reinterpret_cast<float2*>(g.g_probe);
+    d.g_pos = g.g_pos;
+    d.g_sigma = g.g_sigma;
+  }
+  d.var_flat[0] = j.object;
+  d.var_flat[1] = j.probe;
+  d.var_flat[2] = j.pos;
+  d.grad_flat[0] = reinterpret_cast<float*>(d.g_object);
+  d.grad_flat[1] = reinterpret_cast<float*>(d.g_probe);
+  d.grad_flat[2] = d.g_pos;
+  d.grad_flat[3] = d.g_sigma;
+  d.flat_n[0] = 2LL * j.L * j.H * j.W;
+  d.flat_n[1] = 2LL * j.L * j.M * j.N * j.N;
+  d.flat_n[2] = 2LL * j.K;
+  d.flat_n[3] = j.K;
+  d.out = c.out ? c.out[i] : nullptr;
+  d.status = c.status + i;
+  d.loss_k = c.loss_k[i];
+  const int C = c.chunk[i];
+  const size_t N = j.N, L = j.L, M = j.M, plane = N * N;
+  auto take = [&](size_t bytes) {
+    char* r = *cursor;
+    *cursor += align_up(bytes);
+    return r;
+  };
+  d.ramp = reinterpret_cast<float2*>(take(C * 2 * N * sizeof(float2)));
+  d.X = reinterpret_cast<float2*>(take(C * L * plane * sizeof(float2)));
+  d.Y = reinterpret_cast<float2*>(take(C * L * M * plane * sizeof(float2)));
+  if (c.which != 0) {
+    d.GX = reinterpret_cast<float2*>(take(C * L * plane * sizeof(float2)));
+    d.loss_part = reinterpret_cast<float*>(take(C * static_cast<size_t>(n_loss_of(j)) * sizeof(float)));
+    d.dy_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
+    d.sg_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
+    d.dx_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_adj_block(j.N)) * sizeof(float)));
+  }
+  if (has_resample(j)) {
+    d.ibuf = reinterpret_cast<float*>(take(C * plane * sizeof(float)));
+    d.gbuf = reinterpret_cast<float*>(take(C * plane * sizeof(float)));
+  }
+  d.C = C;
+  d.n_loss = n_loss_of(j);
+  d.want_adjoint = wants_adjoint(c, i) ? 1 : 0;
+  if (c.adam) {
+    const ptycho_adam_t& a = c.adam[i];
+    d.adam_m[0] = a.m_object;
+    d.adam_v[0] = a.v_object;
+    d.adam_m[1] = a.m_probe;
+    d.adam_v[1] = a.v_probe;
+    d.adam_m[2] = a.m_pos;
+    d.adam_v[2] = a.v_pos;
+    d.adam_lr[0] = a.lr_object;
+    d.adam_lr[1] = a.lr_probe;
+    d.adam_lr[2] = a.lr_pos;
+    d.adam_beta1 = a.beta1;
+    d.adam_beta2 = a.beta2;
+    d.adam_eps = a.eps;
+    d.adam_bc1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(a.beta1), a.t)));
+    d.adam_bc2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(a.beta2), a.t)));
+  }
 }
 
-#define CHECK_HIP(x)                       \
-  do {                                     \
+// Segments of the launches of one phase, written to the pool in one go.
+struct Phase {
+  std::vector<Seg> segs;
+  struct Item {
+    int first, count;
+    long long units;
+  };
+  Item begin() const { return Item{static_cast<int>(segs.size()), 0, 0}; }
+  void add(Item& it, int job, int l, long long units) {
+    if (units <= 0) return;
+    segs.push_back(Seg{job, l, static_cast<int>(it.units), 0});
+    it.count += 1;
+    it.units += units;
+  }
+};
+
+#define CHECK_HIP(x)                           \
+  do {                                         \
     if ((x) != hipSuccess) return PTYCHO_EHIP; \
   } while (0)
 
@@ -313,6 +451,201 @@ JobDev to_dev(const ptycho_job_t& j) {
     if ((x) != hipSuccess) return PTYCHO_EHIP; \
   } while (0)
 
+int upload_phase(const Call& c, const Phase& ph, hipStream_t s) {
+  if (ph.segs.empty()) return PTYCHO_OK;
+  if (ph.segs.size() > static_cast<size_t>(kSegsPerJob) * c.n) return PTYCHO_EINVAL;
+  LAUNCH(KC_TABLES, launch_write_table(reinterpret_cast<int*>(c.seg_pool),
+                                       reinterpret_cast<const int*>(ph.segs.data()),
+                                       static_cast<int>(ph.segs.size() * sizeof(Seg) / sizeof(int)), s));
+  return PTYCHO_OK;
+}
+
+Launch launch_of(const Call& c, const Phase::Item& it, int iter) {
+  return Launch{c.jobs_dev, c.seg_pool + it.first, it.count, iter};
+}
+
+int run_prologue(Call& c, hipStream_t s) {
+  Phase ph;
+  auto zero = ph.begin();
+  if (c.grads) {
+    for (int i = 0; i < c.n; ++i) {
+      const ptycho_job_t& j = c.jobs[i];
+      const ptycho_grads_t& g = c.grads[i];
+      const size_t sizes[4] = {2ull * j.L * j.H * j.W, 2ull * j.L * j.M * j.N * j.N, 2ull * j.K,
+                               static_cast<size_t>(j.K)};
+      const bool want[4] = {g.g_object != nullptr, g.g_probe != nullptr, g.g_pos != nullptr,
+                            g.g_sigma != nullptr};
+      for (int a = 0; a < 4; ++a)
+        if (want[a]) ph.add(zero, i, a, static_cast<long long>((sizes[a] + 1023) / 1024));
+    }
+  }
+  auto stat = ph.begin();
+  for (int i = 0; i < c.n; ++i) ph.add(stat, i, 0, 1);
+  auto val = ph.begin();
+  for (int i = 0; i < c.n; ++i) ph.add(val, i, 0, (c.jobs[i].K + 255) / 256);
+  int e = upload_phase(c, ph, s);
+  if (e) return e;
+  LAUNCH(KC_FILL, launch_simple(KZeroGrads, launch_of(c, zero, 0), zero.units, s));
+  LAUNCH(KC_PREP, launch_simple(KSetStatus, launch_of(c, stat, 0), stat.units, s));
+  LAUNCH(KC_PREP, launch_simple(KValidate, launch_of(c, val, 0), val.units, s));
+  return PTYCHO_OK;
+}
+
+// One chunk iteration of a group of jobs that share N, resampling and adjoint.
+int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members, int iter,
+                  hipStream_t s) {
+  // positions of each member in this iteration
+  std::vector<int> cnt(members.size());
+  for (size_t q = 0; q < members.size(); ++q) {
+    const ptycho_job_t& j = c.jobs[members[q]];
+    const int k0 = iter * c.chunk[members[q]];
+    cnt[q] = std::max(0, std::min(c.chunk[members[q]], j.K - k0));
+  }
+  const int N = key.N;
+  const size_t plane = static_cast<size_t>(N) * N;
+  Phase ph;
+  auto prep = ph.begin();
+  for (size_t q = 0; q < members.size(); ++q) ph.add(prep, members[q], 0, cnt[q]);
+  auto rowf = ph.begin();
+  for (size_t q = 0; q < members.size(); ++q)
+    for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowf, members[q], l, cnt[q]);
+  // distinct DFT sizes of the group, in first-seen order
+  std::vector<int> nls;
+  for (int i : members)
+    for (int l = 0; l < c.jobs[i].L; ++l)
+      if (std::find(nls.begin(), nls.end(), c.jobs[i].pad[l]) == nls.end()) nls.push_back(c.jobs[i].pad[l]);
+  std::vector<Phase::Item> colf(nls.size()), cola(nls.size());
+  for (size_t p = 0; p < nls.size(); ++p) {
+    colf[p] = ph.begin();
+    for (size_t q = 0; q < members.size(); ++q)
+      for (int l = 0; l < c.jobs[members[q]].L; ++l)
+        if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(colf[p], members[q], l, cnt[q]);
+  }
+  auto det = ph.begin();
+  for (size_t q = 0; q < members.size(); ++q) ph.add(det, members[q], 0, cnt[q]);
+  Phase::Item prob = ph.begin(), rowa = ph.begin(), obj = ph.begin();
+  if (key.adjoint) {
+    for (size_t p = 0; p < nls.size(); ++p) {
+      cola[p] = ph.begin();
+      for (size_t q = 0; q < members.size(); ++q)
+        for (int l = 0; l < c.jobs[members[q]].L; ++l)
+          if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(cola[p], members[q], l, cnt[q]);
+    }
+    prob = ph.begin();
+    const long long nblk = static_cast<long long>((plane + 255) / 256);
+    for (size_t q = 0; q < members.size(); ++q) {
+      if (!cnt[q] || !c.grads[members[q]].g_probe) continue;
+      for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(prob, members[q], l, c.jobs[members[q]].M * nblk);
+    }
+    rowa = ph.begin();
+    for (size_t q = 0; q < members.size(); ++q) {
+      const ptycho_grads_t& g = c.grads[members[q]];
+      if (!(g.g_object || g.g_pos)) continue;
+      for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowa, members[q], l, cnt[q]);
+    }
+    obj = ph.begin();
+    for (size_t q = 0; q < members.size(); ++q) {
+      const ptycho_job_t& j = c.jobs[members[q]];
+      if (!cnt[q] || !c.grads[members[q]].g_object) continue;
+      const long long tiles = static_cast<long long>((j.W + 63) / 64) * ((j.H + 15) / 16);
+      for (int l = 0; l < j.L; ++l) ph.add(obj, members[q], l, tiles);
+    }
+  }
+  auto fin = ph.begin();
+  if (c.which != 0)
+    for (size_t q = 0; q < members.size(); ++q) ph.add(fin, members[q], 0, (cnt[q] + 63) / 64);
+  int e = upload_phase(c, ph, s);
+  if (e) return e;
+
+  LAUNCH(KC_PREP, launch_simple(KPrep, launch_of(c, prep, iter), prep.units, s));
+  LAUNCH(KC_ROW_FWD, launch_row_fwd(N, launch_of(c, rowf, iter), rowf.units, s));
+  for (size_t p = 0; p < nls.size(); ++p)
+    LAUNCH(KC_COL_FWD, launch_col_fwd(N, nls[p], launch_of(c, colf[p], iter), colf[p].units, s));
+  const Launch ldet = launch_of(c, det, iter);
+  if (c.which == 0) {
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, s));
+    if (key.resample) LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, true, s));
+    return PTYCHO_OK;
+  }
+  if (!key.resample) {
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, s));
+  } else {
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, s));
+    LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, false, s));
+    if (key.adjoint) {
+      LAUNCH(KC_RESAMPLE, launch_resample_T(N, ldet, det.units, s));
+      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, s));
+    }
+  }
+  if (key.adjoint) {
+    for (size_t p = 0; p < nls.size(); ++p)
+      LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, s));
+    LAUNCH(KC_PROBE_REDUCE, launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
+    LAUNCH(KC_ROW_ADJ, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));
+    LAUNCH(KC_OBJ_GATHER, launch_simple(KObjGather, launch_of(c, obj, iter), obj.units, s));
+  }
+  LAUNCH(KC_FINALIZE, launch_simple(KFinalize, launch_of(c, fin, iter), fin.units, s));
+  return PTYCHO_OK;
+}
+
+int run_epilogue(Call& c, hipStream_t s) {
+  if (c.which == 0) return PTYCHO_OK;
+  Phase ph;
+  auto tot = ph.begin();
+  for (int i = 0; i < c.n; ++i)
+    if (c.grads[i].loss) ph.add(tot, i, 0, 1);
+  auto ad = ph.begin();
+  if (c.adam) {
+    for (int i = 0; i < c.n; ++i) {
+      const ptycho_job_t& j = c.jobs[i];
+      const ptycho_adam_t& a = c.adam[i];
+      const size_t sizes[3] = {2ull * j.L * j.H * j.W, 2ull * j.L * j.M * j.N * j.N, 2ull * j.K};
+      const float lrs[3] = {a.lr_object, a.lr_probe, a.lr_pos};
+      for (int v = 0; v < 3; ++v)
+        if (lrs[v] != 0.f) ph.add(ad, i, v, static_cast<long long>((sizes[v] + 1023) / 1024));
+    }
+  }
+  int e = upload_phase(c, ph, s);
+  if (e) return e;
+  LAUNCH(KC_FINALIZE, launch_loss_total(launch_of(c, tot, 0), tot.units, c.scale, s));
+  LAUNCH(KC_ADAM, launch_simple(KAdam, launch_of(c, ad, 0), ad.units, s));
+  return PTYCHO_OK;
+}
+
+int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
+  int e = layout(c, ws, ws_bytes);
+  if (e) return e;
+  // groups of jobs sharing every kernel instance
+  std::map<GroupKey, std::vector<int>> groups;
+  for (int i = 0; i < c.n; ++i)
+    groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i)}].push_back(i);
+  c.chunk.assign(c.n, 1);
+  std::map<GroupKey, int> iters;
+  for (auto& kv : groups) {
+    int it = 0;
+    e = plan_chunks(c, kv.second, &it);
+    if (e) return e;
+    iters[kv.first] = it;
+  }
+  // job table: every group reuses the same chunk region (groups run in turn)
+  c.host_jobs.assign(c.n, JobDev{});
+  for (auto& kv : groups) {
+    char* cursor = c.chunk_base;
+    for (int i : kv.second) fill_job(c, i, &cursor);
+  }
+  LAUNCH(KC_TABLES, launch_write_table(reinterpret_cast<int*>(c.jobs_dev),
+                                       reinterpret_cast<const int*>(c.host_jobs.data()),
+                                       static_cast<int>(c.n * sizeof(JobDev) / sizeof(int)), s));
+  e = run_prologue(c, s);
+  if (e) return e;
+  for (auto& kv : groups)
+    for (int it = 0; it < iters[kv.first]; ++it) {
+      e = run_iteration(c, kv.first, kv.second, it, s);
+      if (e) return e;
+    }
+  return run_epilogue(c, s);
+}
+
 int common_checks(const ptycho_job_t* jobs, int n_jobs, bool need_measured) {
   if (!jobs || n_jobs < 1) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i) {
@@ -320,78 +653,6 @@ int common_checks(const ptycho_job_t* jobs, int n_jobs, bool need_measured) {
     if (e) return e;
   }
   return init_twiddles();
-}
-
-int chunk_for(const ptycho_job_t& j, int which, size_t avail) {
-  if (j.K == 0) return 0;
-  const size_t per = per_position_bytes(j, which);
-  const size_t c = avail / per;
-  return static_cast<int>(std::min<size_t>(c, j.K));
-}
-
-// Runs the loss + gradient sequence for one job.
-int run_loss_grad(const ptycho_job_t& job, const ptycho_loss_t& lp, const ptycho_grads_t& g,
-                  int* status, double* loss_k, char* chunk_base, int C, hipStream_t s) {
-  JobDev jb = to_dev(job);
-  const size_t plane = static_cast<size_t>(job.N) * job.N;
-  if (g.g_object) LAUNCH(KC_FILL, launch_fill_zero(g.g_object, 2ull * job.L * job.H * job.W, s));
-  if (g.g_probe) LAUNCH(KC_FILL, launch_fill_zero(g.g_probe, 2ull * job.L * job.M * plane, s));
-  if (g.g_pos) LAUNCH(KC_FILL, launch_fill_zero(g.g_pos, 2ull * job.K, s));
-  if (g.g_sigma) LAUNCH(KC_FILL, launch_fill_zero(g.g_sigma, job.K, s));
-  LAUNCH(KC_PREP, launch_set_status(status, s));
-  LAUNCH(KC_PREP, launch_validate(jb, status, s));
-  const bool want_grad = g.g_object || g.g_probe || g.g_pos || g.g_sigma;
-  LossDev ld{lp.kind, lp.eps, 2.0f * lp.scale};
-  for (int k0 = 0; k0 < job.K; k0 += C) {
-    const int c = std::min(C, job.K - k0);
-    Work w = chunk_views(job, 1, chunk_base, c);
-    w.status = status;
-    w.loss_k = loss_k;
-    w.k0 = k0;
-    LAUNCH(KC_PREP, launch_prep(jb, w, s));
-    for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_FWD, launch_row_fwd(jb, w, l, s));
-    for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_FWD, launch_col_fwd(jb, w, l, s));
-    int n_loss;
-    if (!has_resample(job)) {
-      LAUNCH(KC_DET, launch_det(jb, w, ld, want_grad ? 0 : 3, false, nullptr, s));
-      n_loss = job.N / rows_per_det_block(job.N);
-    } else {
-      LAUNCH(KC_DET, launch_det(jb, w, ld, 1, want_grad, w.ibuf, s));
-      LAUNCH(KC_RESAMPLE, launch_resample_loss(jb, w, ld, nullptr, s));
-      n_loss = static_cast<int>((plane + 255) / 256);
-      if (want_grad) {
-        LAUNCH(KC_RESAMPLE, launch_resample_T(jb, w, s));
-        LAUNCH(KC_DET, launch_det(jb, w, ld, 2, false, nullptr, s));
-      }
-    }
-    if (want_grad) {
-      for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_ADJ, launch_col_adj(jb, w, l, g.g_probe != nullptr, s));
-      if (g.g_probe)
-        LAUNCH(KC_PROBE_REDUCE, launch_probe_reduce(jb, w, reinterpret_cast<float2*>(g.g_probe), s));
-      if (g.g_object || g.g_pos) {
-        for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_ADJ, launch_row_adj(jb, w, l, s));
-      }
-      if (g.g_object) {
-        for (int l = 0; l < job.L; ++l)
-          LAUNCH(KC_OBJ_GATHER, launch_obj_gather(jb, w, l, reinterpret_cast<float2*>(g.g_object), s));
-      }
-    } else {
-      // partial buffers of the adjoint are not produced: keep them zero
-      const size_t nd = static_cast<size_t>(c) * job.L * (job.N / col_group_of(job.N));
-      LAUNCH(KC_FILL, launch_fill_zero(w.dy_part, nd, s));
-      LAUNCH(KC_FILL, launch_fill_zero(w.sg_part, nd, s));
-      LAUNCH(KC_FILL, launch_fill_zero(w.dx_part,
-                                 static_cast<size_t>(c) * job.L * (job.N / rows_per_adj_block(job.N)), s));
-    }
-    LAUNCH(KC_FINALIZE, launch_finalize_chunk(jb, w, n_loss, g.g_pos, g.g_sigma, s));
-  }
-  if (g.loss) {
-    Work w{};
-    w.status = status;
-    w.loss_k = loss_k;
-    LAUNCH(KC_FINALIZE, launch_loss_total(jb, w, lp.scale, g.loss, s));
-  }
-  return PTYCHO_OK;
 }
 
 }  // namespace
@@ -407,12 +668,16 @@ int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t
     const int e = validate_job(jobs[i], false);
     if (e) return e;
   }
-  size_t worst = 0;
+  // chunk region: the largest group needs its jobs' chunks side by side
+  std::map<std::tuple<int, bool>, size_t> group_bytes;
   for (int i = 0; i < n_jobs; ++i) {
     const int K = jobs[i].K;
     const int c = chunk <= 0 ? std::max(K, 1) : std::max(1, std::min<int>(chunk, std::max(K, 1)));
-    worst = std::max(worst, per_position_bytes(jobs[i], which) * static_cast<size_t>(c));
+    group_bytes[std::make_tuple(jobs[i].N, has_resample(jobs[i]))] +=
+        per_position_bytes(jobs[i], which == 0 ? 0 : 1) * static_cast<size_t>(c);
   }
+  size_t worst = 0;
+  for (auto& kv : group_bytes) worst = std::max(worst, kv.second);
   *bytes = fixed_bytes(jobs, n_jobs) + worst;
   return PTYCHO_OK;
 }
@@ -424,40 +689,15 @@ int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* i
   if (!intensity || !workspace) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i)
     if (jobs[i].K > 0 && !intensity[i]) return PTYCHO_EINVAL;
-  Layout lay = make_layout(workspace, workspace_bytes, jobs, n_jobs);
-  std::vector<int> chunks(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) {
-    chunks[i] = chunk_for(jobs[i], 0, lay.chunk_bytes);
-    if (jobs[i].K > 0 && chunks[i] < 1) return PTYCHO_ENOSPC;
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < n_jobs; ++i) {
-    const ptycho_job_t& job = jobs[i];
-    JobDev jb = to_dev(job);
-    int* status = lay.status + i;
-    LAUNCH(KC_PREP, launch_set_status(status, s));
-    LAUNCH(KC_PREP, launch_validate(jb, status, s));
-    const size_t plane = static_cast<size_t>(job.N) * job.N;
-    for (int k0 = 0; k0 < job.K; k0 += chunks[i]) {
-      const int c = std::min(chunks[i], job.K - k0);
-      Work w = chunk_views(job, 0, lay.chunk_base, c);
-      w.status = status;
-      w.loss_k = lay.loss_k;
-      w.k0 = k0;
-      LAUNCH(KC_PREP, launch_prep(jb, w, s));
-      for (int l = 0; l < job.L; ++l) LAUNCH(KC_ROW_FWD, launch_row_fwd(jb, w, l, s));
-      for (int l = 0; l < job.L; ++l) LAUNCH(KC_COL_FWD, launch_col_fwd(jb, w, l, s));
-      LossDev ld{0, 0.f, 0.f};
-      float* out = intensity[i] + static_cast<size_t>(k0) * plane;
-      if (!has_resample(job)) {
-        LAUNCH(KC_DET, launch_det(jb, w, ld, 1, false, out, s));
-      } else {
-        LAUNCH(KC_DET, launch_det(jb, w, ld, 1, false, w.ibuf, s));
-        LAUNCH(KC_RESAMPLE, launch_resample_loss(jb, w, ld, out, s));
-      }
-    }
-  }
-  return PTYCHO_OK;
+  Call c;
+  c.which = 0;
+  c.n = n_jobs;
+  c.jobs = jobs;
+  c.grads = nullptr;
+  c.adam = nullptr;
+  c.out = intensity;
+  c.loss = LossDev{0, 0.f, 0.f};
+  return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_t* loss,
@@ -468,26 +708,27 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
   if (!loss || !grads || !workspace) return PTYCHO_EINVAL;
   if (loss->kind < 0 || loss->kind > 3 || !(loss->eps >= 0.f) || !std::isfinite(loss->scale))
     return PTYCHO_EINVAL;
-  Layout lay = make_layout(workspace, workspace_bytes, jobs, n_jobs);
-  std::vector<int> chunks(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) {
-    chunks[i] = chunk_for(jobs[i], 1, lay.chunk_bytes);
-    if (jobs[i].K > 0 && chunks[i] < 1) return PTYCHO_ENOSPC;
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < n_jobs; ++i) {
-    e = run_loss_grad(jobs[i], *loss, grads[i], lay.status + i, lay.loss_k, lay.chunk_base,
-                      std::max(chunks[i], 1), s);
-    if (e) return e;
-  }
-  return PTYCHO_OK;
+  Call c;
+  c.which = 1;
+  c.n = n_jobs;
+  c.jobs = jobs;
+  c.grads = grads;
+  c.adam = nullptr;
+  c.out = nullptr;
+  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale};
+  c.scale = loss->scale;
+  return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_t* loss,
                     const ptycho_grads_t* grads, const ptycho_adam_t* adam, void* workspace,
                     size_t workspace_bytes, void* stream) {
-  if (!adam || !grads) return PTYCHO_EINVAL;
-  for (int i = 0; n_jobs > 0 && jobs && i < n_jobs; ++i) {
+  int e = common_checks(jobs, n_jobs, true);
+  if (e) return e;
+  if (!loss || !grads || !adam || !workspace) return PTYCHO_EINVAL;
+  if (loss->kind < 0 || loss->kind > 3 || !(loss->eps >= 0.f) || !std::isfinite(loss->scale))
+    return PTYCHO_EINVAL;
+  for (int i = 0; i < n_jobs; ++i) {
     const ptycho_adam_t& a = adam[i];
     if (a.t < 1 || !(a.beta1 >= 0.f && a.beta1 < 1.f) || !(a.beta2 >= 0.f && a.beta2 < 1.f))
       return PTYCHO_EINVAL;
@@ -495,26 +736,16 @@ int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_
     if (a.lr_probe != 0.f && (!a.m_probe || !a.v_probe || !grads[i].g_probe)) return PTYCHO_EINVAL;
     if (a.lr_pos != 0.f && (!a.m_pos || !a.v_pos || !grads[i].g_pos)) return PTYCHO_EINVAL;
   }
-  int e = ptycho_loss_grad(jobs, n_jobs, loss, grads, workspace, workspace_bytes, stream);
-  if (e) return e;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < n_jobs; ++i) {
-    const ptycho_job_t& j = jobs[i];
-    const ptycho_adam_t& a = adam[i];
-    const float bc1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(a.beta1), a.t)));
-    const float bc2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(a.beta2), a.t)));
-    const size_t plane = static_cast<size_t>(j.N) * j.N;
-    if (a.lr_object != 0.f)
-      LAUNCH(KC_ADAM, launch_adam(j.object, grads[i].g_object, a.m_object, a.v_object,
-                            2ull * j.L * j.H * j.W, a.lr_object, a.beta1, a.beta2, a.eps, bc1, bc2, s));
-    if (a.lr_probe != 0.f)
-      LAUNCH(KC_ADAM, launch_adam(j.probe, grads[i].g_probe, a.m_probe, a.v_probe, 2ull * j.L * j.M * plane,
-                            a.lr_probe, a.beta1, a.beta2, a.eps, bc1, bc2, s));
-    if (a.lr_pos != 0.f && j.K > 0)
-      LAUNCH(KC_ADAM, launch_adam(j.pos, grads[i].g_pos, a.m_pos, a.v_pos, 2ull * j.K, a.lr_pos, a.beta1,
-                            a.beta2, a.eps, bc1, bc2, s));
-  }
-  return PTYCHO_OK;
+  Call c;
+  c.which = 2;
+  c.n = n_jobs;
+  c.jobs = jobs;
+  c.grads = grads;
+  c.adam = adam;
+  c.out = nullptr;
+  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale};
+  c.scale = loss->scale;
+  return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 int32_t ptycho_status(const void* workspace, int32_t job, void* stream) {

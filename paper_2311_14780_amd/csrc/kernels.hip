@@ -17,6 +17,13 @@
 //               in ascending k (no atomics)
 //   finalize  : ordered per-position sums of the partials
 // The C ABI (api.cpp) sequences these launches on one stream.
+//
+// Every launch covers the work of one or more jobs: the job descriptors live
+// in device memory (JobDev) and each launch receives a list of segments
+// (job, wavelength, first unit); block b handles unit b / GX, and the
+// segment that contains it names its job and wavelength.  A single job is
+// the one-segment case, so the multi-job (serving) path and the single-job
+// path run the same kernels.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -63,17 +70,6 @@ __device__ __forceinline__ void pad_switch(int nl, const F& f, IntList<P, Ps...>
   }
 }
 
-// Select element l of a small kernel-argument array with constant indices
-// only: a run-time index into a by-value argument would force the whole
-// argument block into registers or scratch.
-template <class T>
-__device__ __forceinline__ T pick(const T (&a)[kMaxL], int l) {
-  T r = a[0];
-#pragma unroll
-  for (int i = 1; i < kMaxL; ++i) r = (l == i) ? a[i] : r;
-  return r;
-}
-
 __device__ __forceinline__ void split_pos(const float* __restrict__ pos, int k, int& py, int& px,
                                           float& dy, float& dx) {
   const float sy = pos[2 * k], sx = pos[2 * k + 1];
@@ -106,19 +102,74 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return s;
 }
 
+
+__device__ __forceinline__ int col_group_of_dev(int N) { return N <= 256 ? 16 : 8; }
+__device__ __forceinline__ int rb_adj_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
+
+// ------------------------------------------------------- work decomposition
+// Largest s with segs[s].unit0 <= unit (segs sorted, segs[0].unit0 == 0).
+// The arguments are wave-uniform, so the search runs on the scalar unit.
+__device__ __forceinline__ int find_seg(const Seg* __restrict__ segs, int nseg, int unit) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].unit0 <= unit) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct UnitRef {
+  const JobDev* jb;
+  int l;      // wavelength (or sub-selector) of the segment
+  int u;      // unit index inside the segment
+  int sub;    // block index inside the unit
+};
+
+template <int GX>
+__device__ __forceinline__ UnitRef decode(const Launch& la) {
+  const int b = blockIdx.x;
+  const int unit = b / GX;
+  const int s = find_seg(la.segs, la.nseg, unit);
+  const Seg sg = la.segs[s];
+  return UnitRef{la.jobs + sg.job, sg.l, unit - sg.unit0, b - unit * GX};
+}
+
+// Copies a table carried in the launch's own argument block to device
+// memory: the payload is the first kernel argument, so it starts at the
+// kernel-argument segment pointer.
+__global__ void k_write_table(TablePayload payload, int* __restrict__ dst, int n) {
+  (void)payload;
+  const __attribute__((address_space(4))) int* src =
+      (const __attribute__((address_space(4))) int*)__builtin_amdgcn_kernarg_segment_ptr();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------ utility
-__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
-  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-  for (size_t j = i; j < n; j += stride) p[j] = v;
+// Zero the requested gradient outputs.  Segment l selects the array
+// (0 object, 1 probe, 2 positions, 3 sigma); units are 1024-float blocks.
+__global__ __launch_bounds__(NT) void k_zero_grads(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  float* __restrict__ p = jb.grad_flat[r.l];
+  const long long n = jb.flat_n[r.l];
+  const long long base = static_cast<long long>(r.u) * 1024;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const long long i = base + threadIdx.x + q * NT;
+    if (i < n) p[i] = 0.f;
+  }
 }
 
-__global__ void k_set_status(int* status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *status = 0;
+__global__ void k_set_status(Launch la) {
+  const UnitRef r = decode<1>(la);
+  if (threadIdx.x == 0) *r.jb->status = 0;
 }
 
-__global__ void k_validate(JobDev jb, int* status) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// units: blocks of 256 positions
+__global__ __launch_bounds__(NT) void k_validate(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  const int k = r.u * NT + threadIdx.x;
   if (k >= jb.K) return;
   const float sy = jb.pos[2 * k], sx = jb.pos[2 * k + 1];
   bool bad = !(isfinite(sy) && isfinite(sx));
@@ -126,51 +177,56 @@ __global__ void k_validate(JobDev jb, int* status) {
     const float fy = floorf(sy + 0.5f), fx = floorf(sx + 0.5f);
     bad = fy < 0.f || fx < 0.f || fy + jb.N > jb.H || fx + jb.N > jb.W;
   }
-  if (bad) *status = kERange;  // every writer stores the same value
+  if (bad) *jb.status = kERange;  // every writer stores the same value
 }
 
 // ramps[c][0][f] = exp(2 pi i nu_f delta_y), ramps[c][1][f] likewise for x
-__global__ void k_prep(JobDev jb, Work w) {
-  if (*w.status) return;
-  const int c = blockIdx.x, k = w.k0 + c;
+__global__ __launch_bounds__(NT) void k_prep(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
+  const int c = r.u, k = la.iter * jb.C + c;
   int py, px;
   float dy, dx;
   split_pos(jb.pos, k, py, px, dy, dx);
   const int N = jb.N;
-  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+  for (int i = threadIdx.x; i < 2 * N; i += NT) {
     const int f = i % N;
     const double d = (i < N) ? static_cast<double>(dy) : static_cast<double>(dx);
     const double nu = static_cast<double>(f < N / 2 ? f : f - N) / N;
     double sn, cs;
     sincospi(2.0 * nu * d, &sn, &cs);
-    w.ramp[static_cast<size_t>(c) * 2 * N + i] = make_float2(static_cast<float>(cs),
-                                                             static_cast<float>(sn));
+    jb.ramp[static_cast<size_t>(c) * 2 * N + i] = make_float2(static_cast<float>(cs),
+                                                              static_cast<float>(sn));
   }
 }
 
 // ------------------------------------------------------------- row forward
 // X[c][l][y][:] = IFFT_x( ramp_x * FFT_x( O_l[p_y + y][p_x : p_x + N] ) ) / N
+// units: (l, c) positions of every wavelength
 template <int N>
-__global__ __launch_bounds__(NT) void k_row_fwd(JobDev jb, Work w, int l) {
-  if (*w.status) return;
+__global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   constexpr int RB = rb_row<N>();
+  const UnitRef r = decode<N / RB>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
   constexpr int LP = row_lp(N);
   using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[RB * LP];
-  const int c = blockIdx.y, k = w.k0 + c;
-  const int y0 = blockIdx.x * RB;
+  const int l = r.l, c = r.u, k = la.iter * jb.C + c;
+  const int y0 = r.sub * RB;
   int py, px;
   float dy, dx;
   split_pos(jb.pos, k, py, px, dy, dx);
   const float2* __restrict__ O =
       jb.object + static_cast<size_t>(l) * jb.H * jb.W + static_cast<size_t>(py + y0) * jb.W + px;
-  const float2* __restrict__ rx = w.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
+  const float2* __restrict__ rx = jb.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
   const float2* __restrict__ tw = jb.tw_N;
   const int Wd = jb.W;
   auto ld_obj = [&](int line, int i) { return O[static_cast<size_t>(line) * Wd + i]; };
   auto st_ramp = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = cmul(v, rx[i]); };
   fft_lines<N, false, RB, NT, LP, false>(buf, tw, ld_obj, st_ramp);
-  float2* __restrict__ X = w.X + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
+  float2* __restrict__ X = jb.X + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
   constexpr float inv = 1.0f / N;
   auto ld_buf = [&](int line, int i) { return buf[Ix::at(line, i)]; };
   auto st_x = [&](int line, int i, float2 v) { X[line * N + i] = cscale(v, inv); };
@@ -179,20 +235,23 @@ __global__ __launch_bounds__(NT) void k_row_fwd(JobDev jb, Work w, int l) {
 
 // ---------------------------------------------------------- column forward
 // Osh = y-shift of X columns; Y_m = (1/sqrt(NL)) crop( DFT_NL_y( sigma P_m Osh ) )
+// units: (l, c) for the wavelengths whose DFT size is NL
 template <int N, int NL>
-__global__ __launch_bounds__(CNT) void k_col_fwd(JobDev jb, Work w, int l) {
-  if (*w.status) return;
+__global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
   constexpr int G = col_group<N>();
+  const UnitRef r = decode<N / G>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
   constexpr int LP = G + 1;
   constexpr int NE = N * G / CNT;
   static_assert(N * G % CNT == 0, "natural layout");
   __shared__ float2 buf[NL * LP];
-  const int c = blockIdx.y, k = w.k0 + c, x0 = blockIdx.x * G;
+  const int l = r.l, c = r.u, k = la.iter * jb.C + c, x0 = r.sub * G;
   const int tid = threadIdx.x;
-  const float2* __restrict__ X = w.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
-  const float2* __restrict__ ry = w.ramp + static_cast<size_t>(c) * 2 * N;
+  const float2* __restrict__ X = jb.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  const float2* __restrict__ ry = jb.ramp + static_cast<size_t>(c) * 2 * N;
   const float2* __restrict__ twN = jb.tw_N;
-  const float2* __restrict__ twL = pick(jb.tw_pad, l);
+  const float2* __restrict__ twL = jb.tw_pad[l];
 
   auto ld_x = [&](int line, int i) { return X[i * N + line]; };
   auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ry[i]); };
@@ -209,7 +268,7 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(JobDev jb, Work w, int l) {
     o[q] = cscale(buf[i * LP + line], sg);
   }
   __syncthreads();
-  const float ps = pick(jb.pad_scale, l);
+  const float ps = jb.pad_scale[l];
   for (int m = 0; m < jb.M; ++m) {
     const float2* __restrict__ P = jb.probe + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
 #pragma unroll
@@ -219,7 +278,7 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(JobDev jb, Work w, int l) {
     }
     __syncthreads();
     float2* __restrict__ Y =
-        w.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
+        jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
     auto ld_psi = [&](int line, int t) {
       return t < N ? buf[t * LP + line] : make_float2(0.f, 0.f);
     };
@@ -272,18 +331,20 @@ __device__ __noinline__ void det_rows_adj(lf2* buf, const lf32* acc, gf2* __rest
 }
 
 // MODE 0: fused forward + loss + adjoint; 1: forward, write I + B to out;
-// 2: adjoint from g rows in w.ibuf; 3: forward + loss only.
+// 2: adjoint from g rows in the resampling buffer; 3: forward + loss only.
 // `spill` (MODE 1) writes Psi back over Y for a later MODE 2.
+// units: positions c
 template <int N, int MODE>
-__global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, bool spill,
-                                            float* __restrict__ out) {
-  if (*w.status) return;
+__global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill) {
   constexpr int RB = rb_det<N>();
+  const UnitRef r = decode<N / RB>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
   constexpr int LPMAX = max_row_lp(typename PadList<N>::type{});
   __shared__ float2 buf[RB * LPMAX];
   __shared__ float acc[RB * N];
   __shared__ float red[NT / 64];
-  const int c = blockIdx.y, k = w.k0 + c, u0 = blockIdx.x * RB;
+  const int c = r.u, k = la.iter * jb.C + c, u0 = r.sub * RB;
   const int tid = threadIdx.x;
   const size_t plane = static_cast<size_t>(N) * N;
 
@@ -292,11 +353,11 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
     __syncthreads();
     const bool keep = (MODE == 0) || (MODE == 1 && spill);
     for (int l = 0; l < jb.L; ++l) {
-      const float ps = pick(jb.pad_scale, l);
-      const float2* twL = pick(jb.tw_pad, l);
-      const int nl = pick(jb.pad, l);
+      const float ps = jb.pad_scale[l];
+      const float2* twL = jb.tw_pad[l];
+      const int nl = jb.pad[l];
       for (int m = 0; m < jb.M; ++m) {
-        float2* Yr = w.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
+        float2* Yr = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
                      static_cast<size_t>(u0) * N;
         pad_switch(nl, [&](auto nlc) {
           constexpr int NL = decltype(nlc)::value;
@@ -312,7 +373,9 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
       float I = acc[e];
       if (jb.background) I += jb.background[pix];
       if (MODE == 1) {
-        out[static_cast<size_t>(c) * plane + pix] = I;
+        // I + B to the resampling buffer, or the final forward output
+        if (jb.ibuf) jb.ibuf[static_cast<size_t>(c) * plane + pix] = I;
+        else jb.out[static_cast<size_t>(k) * plane + pix] = I;
         continue;
       }
       const float meas = jb.measured[static_cast<size_t>(k) * plane + pix];
@@ -338,21 +401,21 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
     }
     if (MODE == 1) return;
     const float s = block_sum(lsum, red);
-    if (tid == 0) w.loss_part[static_cast<size_t>(c) * gridDim.x + blockIdx.x] = s;
+    if (tid == 0) jb.loss_part[static_cast<size_t>(c) * (N / RB) + r.sub] = s;
     if (MODE == 3) return;
   } else {
     for (int e = tid; e < RB * N; e += NT) {
       const int line = e / N, x = e % N;
-      acc[e] = w.ibuf[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
+      acc[e] = jb.ibuf[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
     }
     __syncthreads();
   }
   for (int l = 0; l < jb.L; ++l) {
-    const float ps = pick(jb.pad_scale, l);
-    const float2* twL = pick(jb.tw_pad, l);
-    const int nl = pick(jb.pad, l);
+    const float ps = jb.pad_scale[l];
+    const float2* twL = jb.tw_pad[l];
+    const int nl = jb.pad[l];
     for (int m = 0; m < jb.M; ++m) {
-      float2* Yr = w.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
+      float2* Yr = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
                    static_cast<size_t>(u0) * N;
       pad_switch(nl, [&](auto nlc) {
         constexpr int NL = decltype(nlc)::value;
@@ -365,25 +428,29 @@ __global__ __launch_bounds__(NT) void k_det(JobDev jb, Work w, LossDev loss, boo
 // ----------------------------------------------- tilted-plane resampling
 // out != null: forward, write I' = R(I + B).  Else: loss on I' and
 // gbuf = 2 scale w dloss/dI'.
-__global__ __launch_bounds__(NT) void k_resample_loss(JobDev jb, Work w, LossDev loss,
-                                                      float* __restrict__ out) {
-  if (*w.status) return;
+// units: positions c, NT camera pixels per block (gx blocks per position)
+__global__ __launch_bounds__(NT) void k_resample_loss(Launch la, LossDev loss, bool forward, int gx) {
+  const int unit = blockIdx.x / gx;
+  const int sidx = find_seg(la.segs, la.nseg, unit);
+  const JobDev& jb = la.jobs[la.segs[sidx].job];
+  if (*jb.status) return;
   __shared__ float red[NT / 64];
-  const int c = blockIdx.y, k = w.k0 + c;
+  const int c = unit - la.segs[sidx].unit0, k = la.iter * jb.C + c;
   const int N = jb.N;
   const size_t plane = static_cast<size_t>(N) * N;
-  const int a = blockIdx.x * NT + threadIdx.x;
+  const int sub = blockIdx.x - unit * gx;
+  const int a = sub * NT + threadIdx.x;
   float lsum = 0.f;
   if (a < N * N) {
-    const float* __restrict__ I = w.ibuf + static_cast<size_t>(c) * plane;
+    const float* __restrict__ I = jb.ibuf + static_cast<size_t>(c) * plane;
     float Ip = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int j = min(max(jb.rs_idx[4 * a + t], 0), N * N - 1);  // caller tables are clamped
       Ip = fmaf(jb.rs_w[4 * a + t], I[j], Ip);
     }
-    if (out) {
-      out[static_cast<size_t>(c) * plane + a] = Ip;
+    if (forward) {
+      jb.out[static_cast<size_t>(k) * plane + a] = Ip;
     } else {
       const float meas = jb.measured[static_cast<size_t>(k) * plane + a];
       const float wt = (loss.kind != 3 && jb.mask) ? static_cast<float>(jb.mask[a]) : 1.f;
@@ -404,45 +471,52 @@ __global__ __launch_bounds__(NT) void k_resample_loss(JobDev jb, Work w, LossDev
         dell = meas;
       }
       lsum = wt * ell;
-      w.gbuf[static_cast<size_t>(c) * plane + a] = loss.gscale * wt * dell;
+      jb.gbuf[static_cast<size_t>(c) * plane + a] = loss.gscale * wt * dell;
     }
   }
-  if (out) return;
-  const float s = block_sum(lsum, red);
-  if (threadIdx.x == 0) w.loss_part[static_cast<size_t>(c) * gridDim.x + blockIdx.x] = s;
+  if (forward) return;
+  const float t = block_sum(lsum, red);
+  if (threadIdx.x == 0) jb.loss_part[static_cast<size_t>(c) * gx + sub] = t;
 }
 
 // ibuf[c][j] = sum over the transposed table row j of val * gbuf[c][col]
-__global__ __launch_bounds__(NT) void k_resample_T(JobDev jb, Work w) {
-  if (*w.status) return;
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
+  const int unit = blockIdx.x / gx;
+  const int sidx = find_seg(la.segs, la.nseg, unit);
+  const JobDev& jb = la.jobs[la.segs[sidx].job];
+  if (*jb.status) return;
+  const int c = unit - la.segs[sidx].unit0;
   const int N = jb.N;
   const size_t plane = static_cast<size_t>(N) * N;
-  const int j = blockIdx.x * NT + threadIdx.x;
+  const int j = (blockIdx.x - unit * gx) * NT + threadIdx.x;
   if (j >= N * N) return;
-  const float* __restrict__ g = w.gbuf + static_cast<size_t>(c) * plane;
-  float s = 0.f;
+  const float* __restrict__ g = jb.gbuf + static_cast<size_t>(c) * plane;
+  float acc_s = 0.f;
   const int nnz_max = 4 * N * N;
   const int p0 = min(max(jb.rsT_ptr[j], 0), nnz_max), p1 = min(max(jb.rsT_ptr[j + 1], p0), nnz_max);
-  for (int p = p0; p < p1; ++p) s = fmaf(jb.rsT_val[p], g[min(max(jb.rsT_col[p], 0), N * N - 1)], s);
-  w.ibuf[static_cast<size_t>(c) * plane + j] = s;
+  for (int p = p0; p < p1; ++p) acc_s = fmaf(jb.rsT_val[p], g[min(max(jb.rsT_col[p], 0), N * N - 1)], acc_s);
+  jb.ibuf[static_cast<size_t>(c) * plane + j] = acc_s;
 }
 
 // ---------------------------------------------------------- column adjoint
+// units: (l, c) for the wavelengths whose DFT size is NL
 template <int N, int NL>
-__global__ __launch_bounds__(CNT) void k_col_adj(JobDev jb, Work w, int l, bool want_probe) {
-  if (*w.status) return;
+__global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   constexpr int G = col_group<N>();
+  const UnitRef r = decode<N / G>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
+  const bool want_probe = jb.g_probe != nullptr;
   constexpr int LP = G + 1;
   constexpr int NE = N * G / CNT;
   __shared__ float2 buf[NL * LP];
   __shared__ float red[CNT / 64];
-  const int c = blockIdx.y, k = w.k0 + c, x0 = blockIdx.x * G;
+  const int l = r.l, c = r.u, k = la.iter * jb.C + c, x0 = r.sub * G;
   const int tid = threadIdx.x;
-  const float2* __restrict__ X = w.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
-  const float2* __restrict__ ry = w.ramp + static_cast<size_t>(c) * 2 * N;
+  const float2* __restrict__ X = jb.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  const float2* __restrict__ ry = jb.ramp + static_cast<size_t>(c) * 2 * N;
   const float2* __restrict__ twN = jb.tw_N;
-  const float2* __restrict__ twL = pick(jb.tw_pad, l);
+  const float2* __restrict__ twL = jb.tw_pad[l];
   const float sig = jb.sigma ? jb.sigma[k] : 1.0f;
 
   // recompute Ohat = ramp_y FFT_y(X) and Osh = IFFT_y(Ohat) / N
@@ -467,10 +541,10 @@ __global__ __launch_bounds__(CNT) void k_col_adj(JobDev jb, Work w, int l, bool 
   }
   __syncthreads();
 
-  const float ps = pick(jb.pad_scale, l);
+  const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
   for (int m = 0; m < jb.M; ++m) {
-    float2* __restrict__ Z = w.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
+    float2* __restrict__ Z = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
     const float2* __restrict__ P = jb.probe + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
     auto ld_z = [&](int line, int t) {
       int u = t + N / 2;
@@ -498,7 +572,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(JobDev jb, Work w, int l, bool 
   {
     const float s = block_sum<CNT>(sgsum, red);
     if (tid == 0)
-      w.sg_part[(static_cast<size_t>(c) * jb.L + l) * gridDim.x + blockIdx.x] = s;
+      jb.sg_part[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s;
   }
   // Ghat = FFT_y(G_Osh): y-position derivative and adjoint y-shift
 #pragma unroll
@@ -519,98 +593,111 @@ __global__ __launch_bounds__(CNT) void k_col_adj(JobDev jb, Work w, int l, bool 
     buf[i * LP + line] = cmul(gh, cconj(ry[i]));
   }
   __syncthreads();
-  float2* __restrict__ GX = w.GX + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  float2* __restrict__ GX = jb.GX + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
   auto st_gx = [&](int line, int i, float2 v) { GX[i * N + line] = cscale(v, invN); };
   fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_gx);
   const float s = block_sum<CNT>(dsum, red);
   if (tid == 0)
-    w.dy_part[(static_cast<size_t>(c) * jb.L + l) * gridDim.x + blockIdx.x] = s * invN;
+    jb.dy_part[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s * invN;
 }
 
 // ------------------------------------------- probe gradient: ordered k sum
 // g_probe[l][m][pix] += sum_{c ascending} Y[c][l][m][pix]
-__global__ __launch_bounds__(NT) void k_probe_reduce(JobDev jb, Work w, float2* __restrict__ gp) {
-  if (*w.status) return;
+// units: (l, m * nblk + pixel block), nblk = ceil(N^2 / NT)
+__global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
   const size_t plane = static_cast<size_t>(jb.N) * jb.N;
-  const size_t pix = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
+  const int nblk = static_cast<int>((plane + NT - 1) / NT);
+  const int m = r.u / nblk, blk = r.u - m * nblk;
+  const size_t pix = static_cast<size_t>(blk) * NT + threadIdx.x;
   if (pix >= plane) return;
-  const int lm = blockIdx.y;  // l * M + m
+  const int lm = r.l * jb.M + m;
   const size_t stride = static_cast<size_t>(jb.L) * jb.M * plane;
-  const float2* __restrict__ src = w.Y + static_cast<size_t>(lm) * plane + pix;
+  const float2* __restrict__ src = jb.Y + static_cast<size_t>(lm) * plane + pix;
+  float2* __restrict__ gp = jb.g_probe;
   float2 acc = gp[static_cast<size_t>(lm) * plane + pix];
-  for (int c = 0; c < w.C; ++c) acc = cadd(acc, src[c * stride]);
+  const int C = min(jb.C, jb.K - la.iter * jb.C);
+  for (int c = 0; c < C; ++c) acc = cadd(acc, src[c * stride]);
   gp[static_cast<size_t>(lm) * plane + pix] = acc;
 }
 
 // -------------------------------------------------------------- row adjoint
 // lines [0, RB): G_X rows; [RB, 2 RB): X rows.  x-position derivative from
 // Re sum conj(FFT(G_X)) (2 pi i nu) FFT(X) / N; G_A = IFFT(conj(ramp) FFT(G_X)) / N
+// units: (l, c)
 template <int N>
-__global__ __launch_bounds__(NT) void k_row_adj(JobDev jb, Work w, int l) {
-  if (*w.status) return;
+__global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   constexpr int RB = rb_adj<N>();
+  const UnitRef r = decode<N / RB>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
   constexpr int LP = row_lp(N);
-  using Ix2 = Lds<N, LP, false>;
-  using Ix1 = Lds<N, LP, false>;
+  using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[2 * RB * LP];
   __shared__ float red[NT / 64];
-  const int c = blockIdx.y, y0 = blockIdx.x * RB;
+  const int l = r.l, c = r.u, y0 = r.sub * RB;
   const int tid = threadIdx.x;
   const size_t off = (static_cast<size_t>(c) * jb.L + l) * N * N + static_cast<size_t>(y0) * N;
-  const float2* __restrict__ GXr = w.GX + off;
-  float2* __restrict__ Xr = w.X + off;
-  const float2* __restrict__ rx = w.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
+  const float2* __restrict__ GXr = jb.GX + off;
+  float2* __restrict__ Xr = jb.X + off;
+  const float2* __restrict__ rx = jb.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
   const float2* __restrict__ twN = jb.tw_N;
   auto ld = [&](int line, int i) {
     return line < RB ? GXr[line * N + i] : Xr[(line - RB) * N + i];
   };
-  auto st = [&](int line, int i, float2 v) { buf[Ix2::at(line, i)] = v; };
+  auto st = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = v; };
   fft_lines<N, false, 2 * RB, NT, LP, false>(buf, twN, ld, st);
   float dsum = 0.f;
   for (int e = tid; e < RB * N; e += NT) {
     const int line = e / N, i = e % N;
-    const float2 gh = buf[Ix2::at(line, i)];
-    const float2 xh = buf[Ix2::at(line + RB, i)];
+    const float2 gh = buf[Ix::at(line, i)];
+    const float2 xh = buf[Ix::at(line + RB, i)];
     const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
     dsum += nu * (gh.y * xh.x - gh.x * xh.y);
-    buf[Ix2::at(line, i)] = cmul(gh, cconj(rx[i]));
+    buf[Ix::at(line, i)] = cmul(gh, cconj(rx[i]));
   }
   __syncthreads();
   constexpr float invN = 1.0f / N;
-  auto ld1 = [&](int line, int i) { return buf[Ix1::at(line, i)]; };
+  auto ld1 = [&](int line, int i) { return buf[Ix::at(line, i)]; };
   auto st1 = [&](int line, int i, float2 v) { Xr[line * N + i] = cscale(v, invN); };
   fft_lines<N, true, RB, NT, LP, false>(buf, twN, ld1, st1);
   const float s = block_sum(dsum, red);
-  if (tid == 0) w.dx_part[(static_cast<size_t>(c) * jb.L + l) * gridDim.x + blockIdx.x] = s * invN;
+  if (tid == 0) jb.dx_part[(static_cast<size_t>(c) * jb.L + l) * (N / RB) + r.sub] = s * invN;
 }
 
 // ---------------------------------------------------- object gradient gather
 // Tile of 16 x 64 object pixels; every window of the chunk that overlaps the
 // tile adds its G_A values in ascending k.  No atomics: each pixel has one
-// owner thread, so the sum order is fixed.
+// owner thread, so the sum order is fixed.  units: (l, tile)
 constexpr int kTileW = 64, kTileH = 16;
-__global__ __launch_bounds__(NT) void k_obj_gather(JobDev jb, Work w, int l,
-                                                   float2* __restrict__ gobj) {
-  if (*w.status) return;
-  const int N = jb.N;
-  const int tx0 = blockIdx.x * kTileW, ty0 = blockIdx.y * kTileH;
+__global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
+  const int N = jb.N, l = r.l;
+  const int tiles_x = (jb.W + kTileW - 1) / kTileW;
+  const int ty = r.u / tiles_x, txi = r.u - ty * tiles_x;
+  const int tx0 = txi * kTileW, ty0 = ty * kTileH;
   const int tx = threadIdx.x % kTileW, tyb = threadIdx.x / kTileW;  // tyb in [0, 4)
   const int x = tx0 + tx;
   constexpr int PER = kTileH / (NT / kTileW);
   float2 acc[PER];
-  float2* __restrict__ G = gobj + static_cast<size_t>(l) * jb.H * jb.W;
+  float2* __restrict__ G = jb.g_object + static_cast<size_t>(l) * jb.H * jb.W;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int y = ty0 + tyb + q * (NT / kTileW);
     acc[q] = (x < jb.W && y < jb.H) ? G[static_cast<size_t>(y) * jb.W + x] : make_float2(0.f, 0.f);
   }
   const size_t plane = static_cast<size_t>(N) * N;
-  for (int c = 0; c < w.C; ++c) {
+  const int C = min(jb.C, jb.K - la.iter * jb.C);
+  for (int c = 0; c < C; ++c) {
     int py, px;
     float dy, dx;
-    split_pos(jb.pos, w.k0 + c, py, px, dy, dx);
+    split_pos(jb.pos, la.iter * jb.C + c, py, px, dy, dx);
     if (py >= ty0 + kTileH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0) continue;
-    const float2* __restrict__ GA = w.X + (static_cast<size_t>(c) * jb.L + l) * plane;
+    const float2* __restrict__ GA = jb.X + (static_cast<size_t>(c) * jb.L + l) * plane;
     const int xr = x - px;
     if (xr < 0 || xr >= N) continue;
 #pragma unroll
@@ -627,53 +714,75 @@ __global__ __launch_bounds__(NT) void k_obj_gather(JobDev jb, Work w, int l,
 }
 
 // ---------------------------------------------------------------- finalize
-__global__ void k_finalize_chunk(JobDev jb, Work w, int n_loss, int n_dy, int n_dx,
-                                 float* __restrict__ g_pos, float* __restrict__ g_sigma) {
-  if (*w.status) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= w.C) return;
-  const int k = w.k0 + c;
+// Ordered per-position sums of the partials.  units: blocks of 64 positions
+__global__ void k_finalize_chunk(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*jb.status) return;
+  const int c = r.u * 64 + threadIdx.x;
+  const int C = min(jb.C, jb.K - la.iter * jb.C);
+  if (c >= C) return;
+  const int k = la.iter * jb.C + c;
+  const int n_dy = jb.N / col_group_of_dev(jb.N), n_dx = jb.N / rb_adj_dev(jb.N);
   double ls = 0.0;
-  for (int i = 0; i < n_loss; ++i) ls += w.loss_part[static_cast<size_t>(c) * n_loss + i];
-  w.loss_k[k] = ls;
+  for (int i = 0; i < jb.n_loss; ++i) ls += jb.loss_part[static_cast<size_t>(c) * jb.n_loss + i];
+  jb.loss_k[k] = ls;
+  if (!jb.want_adjoint) return;
   float gy = 0.f, gx = 0.f, gs = 0.f;
   for (int l = 0; l < jb.L; ++l) {
     for (int i = 0; i < n_dy; ++i) {
-      gy += w.dy_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
-      gs += w.sg_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+      gy += jb.dy_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+      gs += jb.sg_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
     }
-    for (int i = 0; i < n_dx; ++i) gx += w.dx_part[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
+    for (int i = 0; i < n_dx; ++i) gx += jb.dx_part[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
   }
-  if (g_pos) {
-    g_pos[2 * k] = gy;
-    g_pos[2 * k + 1] = gx;
+  if (jb.g_pos) {
+    jb.g_pos[2 * k] = gy;
+    jb.g_pos[2 * k + 1] = gx;
   }
-  if (g_sigma) g_sigma[k] = gs;
+  if (jb.g_sigma) jb.g_sigma[k] = gs;
 }
 
-__global__ void k_loss_total(JobDev jb, Work w, float scale, float* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (*w.status) {
-    *loss = __int_as_float(0x7fc00000);
+// one unit per job
+__global__ void k_loss_total(Launch la, float scale) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (threadIdx.x != 0) return;
+  if (*jb.status) {
+    *jb.loss = __int_as_float(0x7fc00000);
     return;
   }
   double s = 0.0;
-  for (int k = 0; k < jb.K; ++k) s += w.loss_k[k];
-  *loss = static_cast<float>(s * scale);
+  for (int k = 0; k < jb.K; ++k) s += jb.loss_k[k];
+  *jb.loss = static_cast<float>(s * scale);
 }
 
-__global__ void k_adam(float* __restrict__ x, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps,
-                       float bc1, float bc2) {
-  const size_t i0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-  for (size_t i = i0; i < n; i += stride) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    x[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+// Adam on real coordinates.  Segment l selects the variable (0 object,
+// 1 probe, 2 positions); units are 1024-float blocks.
+__global__ __launch_bounds__(NT) void k_adam(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  const int v = r.l;
+  float* __restrict__ x = jb.var_flat[v];
+  const float* __restrict__ g = jb.grad_flat[v];
+  float* __restrict__ m = jb.adam_m[v];
+  float* __restrict__ s2 = jb.adam_v[v];
+  const float lr = jb.adam_lr[v];
+  const long long n = jb.flat_n[v];
+  const float b1 = jb.adam_beta1, b2 = jb.adam_beta2, eps = jb.adam_eps;
+  const float bc1 = jb.adam_bc1, bc2 = jb.adam_bc2;
+  const long long base = static_cast<long long>(r.u) * 1024;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const long long i = base + threadIdx.x + q * NT;
+    if (i < n) {
+      const float gi = g[i];
+      const float mi = b1 * m[i] + (1.f - b1) * gi;
+      const float vi = b2 * s2[i] + (1.f - b2) * gi * gi;
+      m[i] = mi;
+      s2[i] = vi;
+      x[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+    }
   }
 }
 
@@ -706,15 +815,6 @@ bool in_list(int nl, IntList<P, Ps...>) {
   return false;
 }
 
-inline unsigned blocks_for(size_t n, unsigned per) {
-  size_t b = (n + per - 1) / per;
-  if (b > 65535u * 8u) b = 65535u * 8u;
-  return static_cast<unsigned>(b < 1 ? 1 : b);
-}
-
-}  // namespace
-
-namespace {
 template <int P, int... Ps>
 int plan_of(int n, int* out, IntList<P, Ps...>) {
   if (n == P) {
@@ -724,6 +824,9 @@ int plan_of(int n, int* out, IntList<P, Ps...>) {
   if constexpr (sizeof...(Ps) > 0) return plan_of(n, out, IntList<Ps...>{});
   return 0;
 }
+
+inline dim3 grid1(long long blocks) { return dim3(static_cast<unsigned>(blocks)); }
+
 }  // namespace
 
 int plan_radices(int n, int* out) {
@@ -743,154 +846,116 @@ bool supported(int N, int nl) {
   }
 }
 
-int rows_per_det_block(int N) {
-  switch (N) {
-    case 64: return rb_det<64>();
-    case 128: return rb_det<128>();
-    case 256: return rb_det<256>();
-    case 384: return rb_det<384>();
-    case 512: return rb_det<512>();
-    default: return 1;
-  }
-}
-int rows_per_adj_block(int N) {
-  switch (N) {
-    case 64: return rb_adj<64>();
-    case 128: return rb_adj<128>();
-    case 256: return rb_adj<256>();
-    case 384: return rb_adj<384>();
-    case 512: return rb_adj<512>();
-    default: return 1;
-  }
-}
+int rows_per_det_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
+int rows_per_adj_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
+int rows_per_row_block(int N) { return N == 64 ? 32 : (N <= 256 ? 16 : 8); }
 int col_group_of(int N) { return N <= 256 ? 16 : 8; }
 
-hipError_t launch_fill_zero(float* p, size_t n, hipStream_t s) { return launch_fill_value(p, n, 0.f, s); }
+hipError_t launch_write_table(int* dst, const int* data, int n, hipStream_t s) {
+  for (int off = 0; off < n; off += kTableInts) {
+    TablePayload p;
+    const int cnt = n - off < kTableInts ? n - off : kTableInts;
+    for (int i = 0; i < cnt; ++i) p.w[i] = data[off + i];
+    hipLaunchKernelGGL(k_write_table, dim3(1), dim3(NT), 0, s, p, dst + off, cnt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
-hipError_t launch_fill_value(float* p, size_t n, float v, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, NT)), dim3(NT), 0, s, p, n, v);
+hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  switch (kind) {
+    case KZeroGrads: hipLaunchKernelGGL(k_zero_grads, grid1(units), dim3(NT), 0, s, la); break;
+    case KSetStatus: hipLaunchKernelGGL(k_set_status, grid1(units), dim3(64), 0, s, la); break;
+    case KValidate: hipLaunchKernelGGL(k_validate, grid1(units), dim3(NT), 0, s, la); break;
+    case KPrep: hipLaunchKernelGGL(k_prep, grid1(units), dim3(NT), 0, s, la); break;
+    case KProbeReduce: hipLaunchKernelGGL(k_probe_reduce, grid1(units), dim3(NT), 0, s, la); break;
+    case KObjGather: hipLaunchKernelGGL(k_obj_gather, grid1(units), dim3(NT), 0, s, la); break;
+    case KFinalize: hipLaunchKernelGGL(k_finalize_chunk, grid1(units), dim3(64), 0, s, la); break;
+    case KAdam: hipLaunchKernelGGL(k_adam, grid1(units), dim3(NT), 0, s, la); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_set_status(int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, status);
+hipError_t launch_loss_total(const Launch& la, long long units, float scale, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loss_total, grid1(units), dim3(64), 0, s, la, scale);
   return hipGetLastError();
 }
 
-hipError_t launch_validate(const JobDev& jb, int* status, hipStream_t s) {
-  if (jb.K == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_validate, dim3((jb.K + NT - 1) / NT), dim3(NT), 0, s, jb, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_prep(const JobDev& jb, const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(w.C), dim3(NT), 0, s, jb, w);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_fwd(const JobDev& jb, const Work& w, int l, hipStream_t s) {
-  return with_N(jb.N, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    hipLaunchKernelGGL(k_row_fwd<N>, dim3(N / rb_row<N>(), w.C), dim3(NT), 0, s, jb, w, l);
+hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    hipLaunchKernelGGL(k_row_fwd<NN>, grid1(units * (NN / rb_row<NN>())), dim3(NT), 0, s, la);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_col_fwd(const JobDev& jb, const Work& w, int l, hipStream_t s) {
-  return with_N(jb.N, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    return host_pad(jb.pad[l], [&](auto pc) {
+hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    return host_pad(nl, [&](auto pc) {
       constexpr int NL = decltype(pc)::value;
-      hipLaunchKernelGGL((k_col_fwd<N, NL>), dim3(N / col_group<N>(), w.C), dim3(CNT), 0, s, jb, w, l);
+      hipLaunchKernelGGL((k_col_fwd<NN, NL>), grid1(units * (NN / col_group<NN>())), dim3(CNT), 0, s, la);
       return hipGetLastError();
-    }, typename PadList<N>::type{});
+    }, typename PadList<NN>::type{});
   });
 }
 
-hipError_t launch_det(const JobDev& jb, const Work& w, const LossDev& loss, int mode, bool spill,
-                      float* out, hipStream_t s) {
-  return with_N(jb.N, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    dim3 grid(N / rb_det<N>(), w.C);
+hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
+                      bool spill, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    const dim3 g = grid1(units * (NN / rb_det<NN>()));
     switch (mode) {
-      case 0: hipLaunchKernelGGL((k_det<N, 0>), grid, dim3(NT), 0, s, jb, w, loss, spill, out); break;
-      case 1: hipLaunchKernelGGL((k_det<N, 1>), grid, dim3(NT), 0, s, jb, w, loss, spill, out); break;
-      case 2: hipLaunchKernelGGL((k_det<N, 2>), grid, dim3(NT), 0, s, jb, w, loss, spill, out); break;
-      default: hipLaunchKernelGGL((k_det<N, 3>), grid, dim3(NT), 0, s, jb, w, loss, spill, out); break;
+      case 0: hipLaunchKernelGGL((k_det<NN, 0>), g, dim3(NT), 0, s, la, loss, spill); break;
+      case 1: hipLaunchKernelGGL((k_det<NN, 1>), g, dim3(NT), 0, s, la, loss, spill); break;
+      case 2: hipLaunchKernelGGL((k_det<NN, 2>), g, dim3(NT), 0, s, la, loss, spill); break;
+      default: hipLaunchKernelGGL((k_det<NN, 3>), g, dim3(NT), 0, s, la, loss, spill); break;
     }
     return hipGetLastError();
   });
 }
 
-hipError_t launch_resample_loss(const JobDev& jb, const Work& w, const LossDev& loss, float* out,
-                                hipStream_t s) {
-  dim3 grid((jb.N * jb.N + NT - 1) / NT, w.C);
-  hipLaunchKernelGGL(k_resample_loss, grid, dim3(NT), 0, s, jb, w, loss, out);
+hipError_t launch_resample_loss(int N, const Launch& la, long long units, const LossDev& loss,
+                                bool forward, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  const int gx = (N * N + NT - 1) / NT;
+  hipLaunchKernelGGL(k_resample_loss, grid1(units * gx), dim3(NT), 0, s, la, loss, forward, gx);
   return hipGetLastError();
 }
 
-hipError_t launch_resample_T(const JobDev& jb, const Work& w, hipStream_t s) {
-  dim3 grid((jb.N * jb.N + NT - 1) / NT, w.C);
-  hipLaunchKernelGGL(k_resample_T, grid, dim3(NT), 0, s, jb, w);
+hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  const int gx = (N * N + NT - 1) / NT;
+  hipLaunchKernelGGL(k_resample_T, grid1(units * gx), dim3(NT), 0, s, la, gx);
   return hipGetLastError();
 }
 
-hipError_t launch_col_adj(const JobDev& jb, const Work& w, int l, bool want_probe, hipStream_t s) {
-  return with_N(jb.N, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    return host_pad(jb.pad[l], [&](auto pc) {
+hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    return host_pad(nl, [&](auto pc) {
       constexpr int NL = decltype(pc)::value;
-      hipLaunchKernelGGL((k_col_adj<N, NL>), dim3(N / col_group<N>(), w.C), dim3(CNT), 0, s, jb, w, l,
-                         want_probe);
+      hipLaunchKernelGGL((k_col_adj<NN, NL>), grid1(units * (NN / col_group<NN>())), dim3(CNT), 0, s, la);
       return hipGetLastError();
-    }, typename PadList<N>::type{});
+    }, typename PadList<NN>::type{});
   });
 }
 
-hipError_t launch_probe_reduce(const JobDev& jb, const Work& w, float2* g_probe, hipStream_t s) {
-  const size_t plane = static_cast<size_t>(jb.N) * jb.N;
-  dim3 grid((plane + NT - 1) / NT, jb.L * jb.M);
-  hipLaunchKernelGGL(k_probe_reduce, grid, dim3(NT), 0, s, jb, w, g_probe);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_adj(const JobDev& jb, const Work& w, int l, hipStream_t s) {
-  return with_N(jb.N, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    hipLaunchKernelGGL(k_row_adj<N>, dim3(N / rb_adj<N>(), w.C), dim3(NT), 0, s, jb, w, l);
+hipError_t launch_row_adj(int N, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    hipLaunchKernelGGL(k_row_adj<NN>, grid1(units * (NN / rb_adj<NN>())), dim3(NT), 0, s, la);
     return hipGetLastError();
   });
-}
-
-hipError_t launch_obj_gather(const JobDev& jb, const Work& w, int l, float2* g_object,
-                             hipStream_t s) {
-  dim3 grid((jb.W + kTileW - 1) / kTileW, (jb.H + kTileH - 1) / kTileH);
-  hipLaunchKernelGGL(k_obj_gather, grid, dim3(NT), 0, s, jb, w, l, g_object);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_chunk(const JobDev& jb, const Work& w, int n_loss, float* g_pos,
-                                 float* g_sigma, hipStream_t s) {
-  const int n_dy = jb.N / col_group_of(jb.N);
-  const int n_dx = jb.N / rows_per_adj_block(jb.N);
-  hipLaunchKernelGGL(k_finalize_chunk, dim3((w.C + 63) / 64), dim3(64), 0, s, jb, w, n_loss, n_dy,
-                     n_dx, g_pos, g_sigma);
-  return hipGetLastError();
-}
-
-hipError_t launch_loss_total(const JobDev& jb, const Work& w, float scale, float* loss,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, jb, w, scale, loss);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(float* x, const float* g, float* m, float* v, size_t n, float lr,
-                       float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n, NT)), dim3(NT), 0, s, x, g, m, v, n, lr, beta1,
-                     beta2, eps, bc1, bc2);
-  return hipGetLastError();
 }
 
 }  // namespace ptycho

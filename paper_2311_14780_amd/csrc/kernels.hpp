@@ -9,8 +9,10 @@ namespace ptycho {
 
 constexpr int kMaxL = 8;
 
-// Job view passed to kernels by value.
+// One job of a call, as seen by the kernels (kept in device memory; every
+// launch reads it through the job index of its work segments).
 struct JobDev {
+  // variables and fixed inputs (caller memory)
   const float2* object;   // [L][H][W]
   const float2* probe;    // [L][M][N][N]
   const float* pos;       // [K][2]
@@ -28,6 +30,59 @@ struct JobDev {
   float pad_scale[kMaxL];  // 1 / sqrt(pad[l])
   const float2* tw_N;            // twiddles of length N
   const float2* tw_pad[kMaxL];   // twiddles of length pad[l]
+  // outputs (caller memory, each may be null)
+  float* loss;
+  float2* g_object;
+  float2* g_probe;
+  float* g_pos;
+  float* g_sigma;
+  float* out;           // forward intensities [K][N][N]
+  // workspace of this job for one chunk of C positions
+  int* status;
+  double* loss_k;       // [K]
+  float2* ramp;         // [C][2][N]    exp(+2 pi i f delta), y then x
+  float2* X;            // [C][L][N][N] row-shifted patch, later G_A
+  float2* Y;            // [C][L][M][N][N] column DFT -> Psi -> Z -> probe-gradient terms
+  float2* GX;           // [C][L][N][N] gradient after the adjoint column shift
+  float* loss_part;     // [C][n_loss]
+  float* dy_part;       // [C][L][N / G]
+  float* sg_part;       // [C][L][N / G]
+  float* dx_part;       // [C][L][N / RBadj]
+  float* ibuf;          // [C][N][N] (resampling only) I + B, then R^T g
+  float* gbuf;          // [C][N][N] (resampling only) weighted dloss/dI'
+  int C;                // positions per chunk (iteration i covers [i C, i C + C))
+  int n_loss;           // loss partials per position
+  int want_adjoint;
+  // Flat float views selected by a segment's l in the gradient-zeroing
+  // (0 object, 1 probe, 2 positions, 3 sigma) and Adam (0..2) launches.
+  // The host fills them so that those kernels pick their arrays by index:
+  // a multi-way branch on l that assigns pointers was compiled into code
+  // that left the pointer registers of the later cases unset.
+  float* var_flat[3];     // object, probe, positions
+  float* grad_flat[4];    // g_object, g_probe, g_pos, g_sigma (may be null)
+  long long flat_n[4];    // floats in each of the four
+  // Adam (ptycho_step)
+  float* adam_m[3];
+  float* adam_v[3];
+  float adam_lr[3];
+  float adam_beta1, adam_beta2, adam_eps, adam_bc1, adam_bc2;
+};
+static_assert(sizeof(JobDev) % sizeof(int) == 0, "the table writer copies whole ints");
+
+// A run of work units of one job (and one wavelength, or sub-selector l).
+struct Seg {
+  int job;
+  int l;
+  int unit0;  // first unit (units of all segments of a launch are numbered 0..)
+  int unused;
+};
+
+// Arguments common to every launch.
+struct Launch {
+  const JobDev* jobs;
+  const Seg* segs;
+  int nseg;
+  int iter;  // chunk index
 };
 
 // Loss parameters as used by the kernels.
@@ -37,22 +92,14 @@ struct LossDev {
   float gscale;  // 2 * scale: folds the factor of G_Psi = 2 g Psi
 };
 
-// Per-chunk workspace views (positions k0 .. k0 + C - 1).
-struct Work {
-  int* status;        // one int for this job
-  float2* ramp;       // [C][2][N]    exp(+2 pi i f delta), y then x
-  float2* X;          // [C][L][N][N] row-shifted patch, later G_A
-  float2* Y;          // [C][L][M][N][N] column DFT -> Psi -> Z -> probe-gradient terms
-  float2* GX;         // [C][L][N][N] gradient after the adjoint column shift
-  float* loss_part;   // [C][N / RBdet]
-  float* dy_part;     // [C][L][N / G]
-  float* sg_part;     // [C][L][N / G]
-  float* dx_part;     // [C][L][N / RBadj]
-  float* ibuf;        // [C][N][N] (resampling only) I + B, then R^T g
-  float* gbuf;        // [C][N][N] (resampling only) weighted dloss/dI'
-  double* loss_k;     // [K] per-position loss (whole job)
-  int k0, C;
+// Kernel-argument payload of the table writer.
+constexpr int kTableInts = 512;
+struct TablePayload {
+  int w[kTableInts];
 };
+
+// Kinds of the simple launches (launch_simple).
+enum SimpleKind { KZeroGrads, KSetStatus, KValidate, KPrep, KProbeReduce, KObjGather, KFinalize, KAdam };
 
 // Radix plan of an FFT length (returns the number of passes, 0 if unknown).
 int plan_radices(int n, int* out);
@@ -65,36 +112,24 @@ void release_twiddles();
 bool supported(int N, int nl);
 int rows_per_det_block(int N);
 int rows_per_adj_block(int N);
+int rows_per_row_block(int N);
 int col_group_of(int N);
 
-// Launchers (all asynchronous on `s`; return hipError_t).
-hipError_t launch_fill_zero(float* p, size_t n, hipStream_t s);
-hipError_t launch_fill_value(float* p, size_t n, float v, hipStream_t s);
-hipError_t launch_set_status(int* status, hipStream_t s);
-hipError_t launch_validate(const JobDev& jb, int* status, hipStream_t s);
-hipError_t launch_prep(const JobDev& jb, const Work& w, hipStream_t s);
-hipError_t launch_row_fwd(const JobDev& jb, const Work& w, int l, hipStream_t s);
-hipError_t launch_col_fwd(const JobDev& jb, const Work& w, int l, hipStream_t s);
-// mode: 0 fused loss+adjoint, 1 forward -> write I + B to `out` (spill: keep Psi),
-//       2 adjoint from ibuf (R^T g), 3 loss only (no adjoint)
-hipError_t launch_det(const JobDev& jb, const Work& w, const LossDev& loss, int mode, bool spill,
-                      float* out, hipStream_t s);
-hipError_t launch_resample_loss(const JobDev& jb, const Work& w, const LossDev& loss,
-                                float* out, hipStream_t s);
-hipError_t launch_resample_T(const JobDev& jb, const Work& w, hipStream_t s);
-hipError_t launch_col_adj(const JobDev& jb, const Work& w, int l, bool want_probe,
-                          hipStream_t s);
-hipError_t launch_probe_reduce(const JobDev& jb, const Work& w, float2* g_probe, hipStream_t s);
-hipError_t launch_row_adj(const JobDev& jb, const Work& w, int l, hipStream_t s);
-hipError_t launch_obj_gather(const JobDev& jb, const Work& w, int l, float2* g_object,
-                             hipStream_t s);
-// n_loss: loss partials per position (N / rows_per_det_block, or the
-// resampling kernel's block count)
-hipError_t launch_finalize_chunk(const JobDev& jb, const Work& w, int n_loss, float* g_pos,
-                                 float* g_sigma, hipStream_t s);
-hipError_t launch_loss_total(const JobDev& jb, const Work& w, float scale, float* loss,
-                             hipStream_t s);
-hipError_t launch_adam(float* x, const float* g, float* m, float* v, size_t n, float lr,
-                       float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+// Launchers (asynchronous on `s`).  `units` is the total number of work
+// units of the launch's segments.
+hipError_t launch_write_table(int* dst, const int* data, int n, hipStream_t s);
+hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_t s);
+hipError_t launch_loss_total(const Launch& la, long long units, float scale, hipStream_t s);
+hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t s);
+hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s);
+// mode: 0 fused loss + adjoint, 1 forward (I + B to ibuf or out; `spill`
+// keeps Psi for mode 2), 2 adjoint from ibuf (R^T g), 3 loss only
+hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
+                      bool spill, hipStream_t s);
+hipError_t launch_resample_loss(int N, const Launch& la, long long units, const LossDev& loss,
+                                bool forward, hipStream_t s);
+hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream_t s);
+hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, hipStream_t s);
+hipError_t launch_row_adj(int N, const Launch& la, long long units, hipStream_t s);
 
 }  // namespace ptycho

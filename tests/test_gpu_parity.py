@@ -120,3 +120,51 @@ def test_window_outside_object_reports_erange(c1):
     prob.pos = U.to_problem(c1, DEV).pos
     got = U.gpu_grads(prob)
     assert B.ptycho_status(got["_ws"], 0) == B.PTYCHO_OK
+
+
+def test_heterogeneous_jobs_in_one_fused_call():
+    """Jobs of different sizes, wavelength and mode counts, pads, chunking
+    and requested outputs share the launches of one call; each job's results
+    are bitwise identical to running it alone."""
+    from paper_2311_14780_amd import binding as B
+    base = synth.get_workload("C1")
+    specs = [
+        dict(w=synth.reduced(base, K=7, name="h1"), pads=None, want=("object", "probe", "pos", "sigma")),
+        dict(w=synth.reduced(base, K=11, L=2, M=3, harmonics=(21, 23), mode_weights=(0.6, 0.3, 0.1),
+                             seed=21, name="h2"), pads=(72, 64), want=("object", "pos")),
+        dict(w=synth.reduced(base, K=5, L=3, M=2, harmonics=(19, 21, 23), mode_weights=(0.7, 0.3),
+                             seed=22, name="h3"), pads=(90, 80, 64), want=("probe",)),
+        dict(w=synth.reduced(synth.get_workload("C2"), K=3, L=2, M=2, harmonics=(21, 23),
+                             mode_weights=(0.6, 0.4), seed=23, name="h4"), pads=(280, 256),
+             want=("object", "probe", "pos", "sigma")),
+    ]
+    probs, singles, gs = [], [], []
+    for sp in specs:
+        case = U.make_case(sp["w"], pads=sp["pads"], with_sigma=True)
+        p = U.to_problem(case, DEV)
+        probs.append(p)
+        singles.append(U.gpu_grads(p, want=sp["want"]))
+        g = dict(loss=torch.zeros(1, device=DEV))
+        if "object" in sp["want"]:
+            g["g_object"] = torch.zeros_like(p.object)
+        if "probe" in sp["want"]:
+            g["g_probe"] = torch.zeros_like(p.probe)
+        if "pos" in sp["want"]:
+            g["g_pos"] = torch.zeros(p.K, 2, device=DEV)
+        if "sigma" in sp["want"]:
+            g["g_sigma"] = torch.zeros(p.K, device=DEV)
+        gs.append(g)
+    ws = B.workspace(probs, 1, chunk=4)  # forces several chunk iterations
+    B.ptycho_loss_grad(probs, gs, workspace=ws)
+    torch.cuda.synchronize()
+    for single, g in zip(singles, gs):
+        assert single["loss"] == float(g["loss"].item())
+        for k, v in g.items():
+            if k != "loss":
+                assert np.array_equal(single[k], v.cpu().numpy()), k
+    # and the forward of the same mix
+    outs = [torch.empty(p.K, p.N, p.N, device=DEV) for p in probs]
+    B.ptycho_forward(probs, outs, B.workspace(probs, 0))
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        assert np.array_equal(U.gpu_forward(p), o.cpu().numpy())
