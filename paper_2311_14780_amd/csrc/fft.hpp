@@ -20,9 +20,12 @@
 
 namespace ptycho {
 
-// Address-space qualified pointers for out-of-line device functions, whose
-// generic pointer arguments would otherwise be accessed with flat
-// instructions (flat loads also hold the LDS wait counter).
+// Address-space qualified pointers.  Pointers that reach a kernel through
+// memory (the job table) or through an out-of-line function's arguments are
+// generic, and generic accesses compile to flat instructions, which also
+// hold the LDS wait counter: every LDS wait of an FFT pass would then wait
+// for outstanding HBM traffic too.  Kernels therefore convert such pointers
+// with gmem() and access complex data through ldv/stv.
 // Complex values behind such pointers use the native two-float vector type.
 #define PTYCHO_GLOBAL __attribute__((address_space(1)))
 #define PTYCHO_LDS __attribute__((address_space(3)))
@@ -30,6 +33,14 @@ using vf2 = float __attribute__((ext_vector_type(2)));
 using gf2 = PTYCHO_GLOBAL vf2;
 using lf2 = PTYCHO_LDS vf2;
 using lf32 = PTYCHO_LDS float;
+using gf32 = PTYCHO_GLOBAL float;
+
+__device__ __forceinline__ gf2* gmem(float2* p) { return (gf2*)p; }
+__device__ __forceinline__ const gf2* gmem(const float2* p) { return (const gf2*)p; }
+template <class T>
+__device__ __forceinline__ PTYCHO_GLOBAL T* gmem(T* p) { return (PTYCHO_GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ const PTYCHO_GLOBAL T* gmem(const T* p) { return (const PTYCHO_GLOBAL T*)p; }
 
 // Element access that works for generic float2 pointers and for the
 // address-space qualified vector pointers above.
@@ -38,13 +49,15 @@ __device__ __forceinline__ float2 ldv(const lf2* p, int i) {
   const vf2 t = p[i];
   return make_float2(t.x, t.y);
 }
-__device__ __forceinline__ float2 ldv(const gf2* p, int i) {
+template <class I>
+__device__ __forceinline__ float2 ldv(const gf2* p, I i) {
   const vf2 t = p[i];
   return make_float2(t.x, t.y);
 }
 __device__ __forceinline__ void stv(float2* p, int i, float2 v) { p[i] = v; }
 __device__ __forceinline__ void stv(lf2* p, int i, float2 v) { p[i] = vf2{v.x, v.y}; }
-__device__ __forceinline__ void stv(gf2* p, int i, float2 v) { p[i] = vf2{v.x, v.y}; }
+template <class I>
+__device__ __forceinline__ void stv(gf2* p, I i, float2 v) { p[i] = vf2{v.x, v.y}; }
 
 // ----------------------------------------------------------- complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -430,14 +443,13 @@ __device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, cons
   // The twiddle base is made opaque here so that the compiler cannot hoist
   // the (loop-invariant) twiddle loads of an FFT out of an enclosing loop,
   // which would pin every twiddle value in registers for the whole loop.
-  {
-    const unsigned long long a = reinterpret_cast<unsigned long long>(tw);
-    unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
-    unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
-    asm volatile("" : "+s"(lo), "+s"(hi));
-    tw = reinterpret_cast<Tw>((static_cast<unsigned long long>(hi) << 32) | lo);
-  }
-  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
+  // The table lives in global memory: the rebuilt pointer says so.
+  const unsigned long long a = reinterpret_cast<unsigned long long>(tw);
+  unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+  unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  const gf2* tg = reinterpret_cast<const gf2*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, load, store,
                                                               typename Plan<n>::type{});
 }
 

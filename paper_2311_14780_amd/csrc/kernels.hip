@@ -70,7 +70,7 @@ __device__ __forceinline__ void pad_switch(int nl, const F& f, IntList<P, Ps...>
   }
 }
 
-__device__ __forceinline__ void split_pos(const float* __restrict__ pos, int k, int& py, int& px,
+__device__ __forceinline__ void split_pos(const gf32* __restrict__ pos, int k, int& py, int& px,
                                           float& dy, float& dx) {
   const float sy = pos[2 * k], sx = pos[2 * k + 1];
   const float fy = floorf(sy + 0.5f), fx = floorf(sx + 0.5f);
@@ -150,7 +150,7 @@ __global__ void k_write_table(TablePayload payload, int* __restrict__ dst, int n
 __global__ __launch_bounds__(NT) void k_zero_grads(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
-  float* __restrict__ p = jb.grad_flat[r.l];
+  gf32* __restrict__ p = gmem(jb.grad_flat[r.l]);
   const long long n = jb.flat_n[r.l];
   const long long base = static_cast<long long>(r.u) * 1024;
 #pragma unroll
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT) void k_zero_grads(Launch la) {
 
 __global__ void k_set_status(Launch la) {
   const UnitRef r = decode<1>(la);
-  if (threadIdx.x == 0) *r.jb->status = 0;
+  if (threadIdx.x == 0) *gmem(r.jb->status) = 0;
 }
 
 // units: blocks of 256 positions
@@ -171,24 +171,25 @@ __global__ __launch_bounds__(NT) void k_validate(Launch la) {
   const JobDev& jb = *r.jb;
   const int k = r.u * NT + threadIdx.x;
   if (k >= jb.K) return;
-  const float sy = jb.pos[2 * k], sx = jb.pos[2 * k + 1];
+  const gf32* pos = gmem(jb.pos);
+  const float sy = pos[2 * k], sx = pos[2 * k + 1];
   bool bad = !(isfinite(sy) && isfinite(sx));
   if (!bad) {
     const float fy = floorf(sy + 0.5f), fx = floorf(sx + 0.5f);
     bad = fy < 0.f || fx < 0.f || fy + jb.N > jb.H || fx + jb.N > jb.W;
   }
-  if (bad) *jb.status = kERange;  // every writer stores the same value
+  if (bad) *gmem(jb.status) = kERange;  // every writer stores the same value
 }
 
 // ramps[c][0][f] = exp(2 pi i nu_f delta_y), ramps[c][1][f] likewise for x
 __global__ __launch_bounds__(NT) void k_prep(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const int c = r.u, k = la.iter * jb.C + c;
   int py, px;
   float dy, dx;
-  split_pos(jb.pos, k, py, px, dy, dx);
+  split_pos(gmem(jb.pos), k, py, px, dy, dx);
   const int N = jb.N;
   for (int i = threadIdx.x; i < 2 * N; i += NT) {
     const int f = i % N;
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(NT) void k_prep(Launch la) {
     const double nu = static_cast<double>(f < N / 2 ? f : f - N) / N;
     double sn, cs;
     sincospi(2.0 * nu * d, &sn, &cs);
-    jb.ramp[static_cast<size_t>(c) * 2 * N + i] = make_float2(static_cast<float>(cs),
-                                                              static_cast<float>(sn));
+    stv(gmem(jb.ramp), static_cast<size_t>(c) * 2 * N + i,
+        make_float2(static_cast<float>(cs), static_cast<float>(sn)));
   }
 }
 
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   constexpr int RB = rb_row<N>();
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   constexpr int LP = row_lp(N);
   using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[RB * LP];
@@ -217,19 +218,19 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   const int y0 = r.sub * RB;
   int py, px;
   float dy, dx;
-  split_pos(jb.pos, k, py, px, dy, dx);
-  const float2* __restrict__ O =
-      jb.object + static_cast<size_t>(l) * jb.H * jb.W + static_cast<size_t>(py + y0) * jb.W + px;
-  const float2* __restrict__ rx = jb.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
+  split_pos(gmem(jb.pos), k, py, px, dy, dx);
+  const gf2* __restrict__ O = gmem(jb.object) + static_cast<size_t>(l) * jb.H * jb.W +
+                              static_cast<size_t>(py + y0) * jb.W + px;
+  const gf2* __restrict__ rx = gmem(jb.ramp) + (static_cast<size_t>(c) * 2 + 1) * N;
   const float2* __restrict__ tw = jb.tw_N;
   const int Wd = jb.W;
-  auto ld_obj = [&](int line, int i) { return O[static_cast<size_t>(line) * Wd + i]; };
-  auto st_ramp = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = cmul(v, rx[i]); };
+  auto ld_obj = [&](int line, int i) { return ldv(O, line * Wd + i); };
+  auto st_ramp = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = cmul(v, ldv(rx, i)); };
   fft_lines<N, false, RB, NT, LP, false>(buf, tw, ld_obj, st_ramp);
-  float2* __restrict__ X = jb.X + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
+  gf2* __restrict__ X = gmem(jb.X) + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
   constexpr float inv = 1.0f / N;
   auto ld_buf = [&](int line, int i) { return buf[Ix::at(line, i)]; };
-  auto st_x = [&](int line, int i, float2 v) { X[line * N + i] = cscale(v, inv); };
+  auto st_x = [&](int line, int i, float2 v) { stv(X, line * N + i, cscale(v, inv)); };
   fft_lines<N, true, RB, NT, LP, false>(buf, tw, ld_buf, st_x);
 }
 
@@ -241,26 +242,26 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
   constexpr int G = col_group<N>();
   const UnitRef r = decode<N / G>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   constexpr int LP = G + 1;
   constexpr int NE = N * G / CNT;
   static_assert(N * G % CNT == 0, "natural layout");
   __shared__ float2 buf[NL * LP];
   const int l = r.l, c = r.u, k = la.iter * jb.C + c, x0 = r.sub * G;
   const int tid = threadIdx.x;
-  const float2* __restrict__ X = jb.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
-  const float2* __restrict__ ry = jb.ramp + static_cast<size_t>(c) * 2 * N;
+  const gf2* __restrict__ X = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
   const float2* __restrict__ twN = jb.tw_N;
   const float2* __restrict__ twL = jb.tw_pad[l];
 
-  auto ld_x = [&](int line, int i) { return X[i * N + line]; };
-  auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ry[i]); };
+  auto ld_x = [&](int line, int i) { return ldv(X, i * N + line); };
+  auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ldv(ry, i)); };
   fft_lines<N, false, G, CNT, LP, true>(buf, twN, ld_x, st_ramp);
   auto ld_buf = [&](int line, int i) { return buf[i * LP + line]; };
   auto st_buf = [&](int line, int i, float2 v) { buf[i * LP + line] = v; };
   fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_buf);
 
-  const float sg = (jb.sigma ? jb.sigma[k] : 1.0f) / N;
+  const float sg = (jb.sigma ? gmem(jb.sigma)[k] : 1.0f) / N;
   float2 o[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
@@ -270,22 +271,22 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
   __syncthreads();
   const float ps = jb.pad_scale[l];
   for (int m = 0; m < jb.M; ++m) {
-    const float2* __restrict__ P = jb.probe + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
+    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * CNT, line = e % G, i = e / G;
-      buf[i * LP + line] = cmul(P[i * N + line], o[q]);
+      buf[i * LP + line] = cmul(ldv(P, i * N + line), o[q]);
     }
     __syncthreads();
-    float2* __restrict__ Y =
-        jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
+    gf2* __restrict__ Y =
+        gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
     auto ld_psi = [&](int line, int t) {
       return t < N ? buf[t * LP + line] : make_float2(0.f, 0.f);
     };
     auto st_y = [&](int line, int t, float2 v) {
       int u = t + N / 2;
       if (u >= NL) u -= NL;
-      if (u < N) Y[u * N + line] = cscale(v, ps);
+      if (u < N) stv(Y, u * N + line, cscale(v, ps));
     };
     fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_psi, st_y);
   }
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
   constexpr int RB = rb_det<N>();
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   constexpr int LPMAX = max_row_lp(typename PadList<N>::type{});
   __shared__ float2 buf[RB * LPMAX];
   __shared__ float acc[RB * N];
@@ -357,11 +358,11 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
       const float2* twL = jb.tw_pad[l];
       const int nl = jb.pad[l];
       for (int m = 0; m < jb.M; ++m) {
-        float2* Yr = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
-                     static_cast<size_t>(u0) * N;
+        gf2* Yr = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
+                  static_cast<size_t>(u0) * N;
         pad_switch(nl, [&](auto nlc) {
           constexpr int NL = decltype(nlc)::value;
-          det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, (gf2*)Yr, (const gf2*)twL, ps, keep);
+          det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), ps, keep);
         }, typename PadList<N>::type{});
       }
     }
@@ -371,15 +372,15 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
       const int line = e / N, x = e % N;
       const int pix = (u0 + line) * N + x;
       float I = acc[e];
-      if (jb.background) I += jb.background[pix];
+      if (jb.background) I += gmem(jb.background)[pix];
       if (MODE == 1) {
         // I + B to the resampling buffer, or the final forward output
-        if (jb.ibuf) jb.ibuf[static_cast<size_t>(c) * plane + pix] = I;
-        else jb.out[static_cast<size_t>(k) * plane + pix] = I;
+        if (jb.ibuf) gmem(jb.ibuf)[static_cast<size_t>(c) * plane + pix] = I;
+        else gmem(jb.out)[static_cast<size_t>(k) * plane + pix] = I;
         continue;
       }
-      const float meas = jb.measured[static_cast<size_t>(k) * plane + pix];
-      const float wt = (loss.kind != 3 && jb.mask) ? static_cast<float>(jb.mask[pix]) : 1.f;
+      const float meas = gmem(jb.measured)[static_cast<size_t>(k) * plane + pix];
+      const float wt = (loss.kind != 3 && jb.mask) ? static_cast<float>(gmem(jb.mask)[pix]) : 1.f;
       float ell, dell;
       if (loss.kind == 0) {
         const float a = sqrtf(I + loss.eps), b = sqrtf(meas + loss.eps);
@@ -401,12 +402,12 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
     }
     if (MODE == 1) return;
     const float s = block_sum(lsum, red);
-    if (tid == 0) jb.loss_part[static_cast<size_t>(c) * (N / RB) + r.sub] = s;
+    if (tid == 0) gmem(jb.loss_part)[static_cast<size_t>(c) * (N / RB) + r.sub] = s;
     if (MODE == 3) return;
   } else {
     for (int e = tid; e < RB * N; e += NT) {
       const int line = e / N, x = e % N;
-      acc[e] = jb.ibuf[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
+      acc[e] = gmem(jb.ibuf)[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
     }
     __syncthreads();
   }
@@ -415,11 +416,11 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
     const float2* twL = jb.tw_pad[l];
     const int nl = jb.pad[l];
     for (int m = 0; m < jb.M; ++m) {
-      float2* Yr = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
-                   static_cast<size_t>(u0) * N;
+      gf2* Yr = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
+                static_cast<size_t>(u0) * N;
       pad_switch(nl, [&](auto nlc) {
         constexpr int NL = decltype(nlc)::value;
-        det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, (gf2*)Yr, (const gf2*)twL, ps);
+        det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
       }, typename PadList<N>::type{});
     }
   }
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_resample_loss(Launch la, LossDev loss, b
   const int unit = blockIdx.x / gx;
   const int sidx = find_seg(la.segs, la.nseg, unit);
   const JobDev& jb = la.jobs[la.segs[sidx].job];
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   __shared__ float red[NT / 64];
   const int c = unit - la.segs[sidx].unit0, k = la.iter * jb.C + c;
   const int N = jb.N;
@@ -442,18 +443,20 @@ __global__ __launch_bounds__(NT) void k_resample_loss(Launch la, LossDev loss, b
   const int a = sub * NT + threadIdx.x;
   float lsum = 0.f;
   if (a < N * N) {
-    const float* __restrict__ I = jb.ibuf + static_cast<size_t>(c) * plane;
+    const gf32* __restrict__ I = gmem(jb.ibuf) + static_cast<size_t>(c) * plane;
+    const PTYCHO_GLOBAL int32_t* __restrict__ ridx = gmem(jb.rs_idx);
+    const gf32* __restrict__ rw = gmem(jb.rs_w);
     float Ip = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int j = min(max(jb.rs_idx[4 * a + t], 0), N * N - 1);  // caller tables are clamped
-      Ip = fmaf(jb.rs_w[4 * a + t], I[j], Ip);
+      const int j = min(max(ridx[4 * a + t], 0), N * N - 1);  // caller tables are clamped
+      Ip = fmaf(rw[4 * a + t], I[j], Ip);
     }
     if (forward) {
-      jb.out[static_cast<size_t>(k) * plane + a] = Ip;
+      gmem(jb.out)[static_cast<size_t>(k) * plane + a] = Ip;
     } else {
-      const float meas = jb.measured[static_cast<size_t>(k) * plane + a];
-      const float wt = (loss.kind != 3 && jb.mask) ? static_cast<float>(jb.mask[a]) : 1.f;
+      const float meas = gmem(jb.measured)[static_cast<size_t>(k) * plane + a];
+      const float wt = (loss.kind != 3 && jb.mask) ? static_cast<float>(gmem(jb.mask)[a]) : 1.f;
       float ell, dell;
       if (loss.kind == 0) {
         const float x = sqrtf(Ip + loss.eps), y = sqrtf(meas + loss.eps);
@@ -471,12 +474,12 @@ __global__ __launch_bounds__(NT) void k_resample_loss(Launch la, LossDev loss, b
         dell = meas;
       }
       lsum = wt * ell;
-      jb.gbuf[static_cast<size_t>(c) * plane + a] = loss.gscale * wt * dell;
+      gmem(jb.gbuf)[static_cast<size_t>(c) * plane + a] = loss.gscale * wt * dell;
     }
   }
   if (forward) return;
   const float t = block_sum(lsum, red);
-  if (threadIdx.x == 0) jb.loss_part[static_cast<size_t>(c) * gx + sub] = t;
+  if (threadIdx.x == 0) gmem(jb.loss_part)[static_cast<size_t>(c) * gx + sub] = t;
 }
 
 // ibuf[c][j] = sum over the transposed table row j of val * gbuf[c][col]
@@ -484,18 +487,21 @@ __global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
   const int unit = blockIdx.x / gx;
   const int sidx = find_seg(la.segs, la.nseg, unit);
   const JobDev& jb = la.jobs[la.segs[sidx].job];
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const int c = unit - la.segs[sidx].unit0;
   const int N = jb.N;
   const size_t plane = static_cast<size_t>(N) * N;
   const int j = (blockIdx.x - unit * gx) * NT + threadIdx.x;
   if (j >= N * N) return;
-  const float* __restrict__ g = jb.gbuf + static_cast<size_t>(c) * plane;
+  const gf32* __restrict__ g = gmem(jb.gbuf) + static_cast<size_t>(c) * plane;
+  const PTYCHO_GLOBAL int32_t* __restrict__ tptr = gmem(jb.rsT_ptr);
+  const PTYCHO_GLOBAL int32_t* __restrict__ tcol = gmem(jb.rsT_col);
+  const gf32* __restrict__ tval = gmem(jb.rsT_val);
   float acc_s = 0.f;
   const int nnz_max = 4 * N * N;
-  const int p0 = min(max(jb.rsT_ptr[j], 0), nnz_max), p1 = min(max(jb.rsT_ptr[j + 1], p0), nnz_max);
-  for (int p = p0; p < p1; ++p) acc_s = fmaf(jb.rsT_val[p], g[min(max(jb.rsT_col[p], 0), N * N - 1)], acc_s);
-  jb.ibuf[static_cast<size_t>(c) * plane + j] = acc_s;
+  const int p0 = min(max(tptr[j], 0), nnz_max), p1 = min(max(tptr[j + 1], p0), nnz_max);
+  for (int p = p0; p < p1; ++p) acc_s = fmaf(tval[p], g[min(max(tcol[p], 0), N * N - 1)], acc_s);
+  gmem(jb.ibuf)[static_cast<size_t>(c) * plane + j] = acc_s;
 }
 
 // ---------------------------------------------------------- column adjoint
@@ -505,7 +511,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   constexpr int G = col_group<N>();
   const UnitRef r = decode<N / G>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const bool want_probe = jb.g_probe != nullptr;
   constexpr int LP = G + 1;
   constexpr int NE = N * G / CNT;
@@ -513,15 +519,15 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   __shared__ float red[CNT / 64];
   const int l = r.l, c = r.u, k = la.iter * jb.C + c, x0 = r.sub * G;
   const int tid = threadIdx.x;
-  const float2* __restrict__ X = jb.X + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
-  const float2* __restrict__ ry = jb.ramp + static_cast<size_t>(c) * 2 * N;
+  const gf2* __restrict__ X = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
   const float2* __restrict__ twN = jb.tw_N;
   const float2* __restrict__ twL = jb.tw_pad[l];
-  const float sig = jb.sigma ? jb.sigma[k] : 1.0f;
+  const float sig = jb.sigma ? gmem(jb.sigma)[k] : 1.0f;
 
   // recompute Ohat = ramp_y FFT_y(X) and Osh = IFFT_y(Ohat) / N
-  auto ld_x = [&](int line, int i) { return X[i * N + line]; };
-  auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ry[i]); };
+  auto ld_x = [&](int line, int i) { return ldv(X, i * N + line); };
+  auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ldv(ry, i)); };
   fft_lines<N, false, G, CNT, LP, true>(buf, twN, ld_x, st_ramp);
   float2 ohat[NE], o[NE], go[NE];
 #pragma unroll
@@ -544,12 +550,12 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
   for (int m = 0; m < jb.M; ++m) {
-    float2* __restrict__ Z = jb.Y + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
-    const float2* __restrict__ P = jb.probe + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
+    gf2* __restrict__ Z = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
+    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
     auto ld_z = [&](int line, int t) {
       int u = t + N / 2;
       if (u >= NL) u -= NL;
-      return u < N ? Z[u * N + line] : make_float2(0.f, 0.f);
+      return u < N ? ldv(Z, u * N + line) : make_float2(0.f, 0.f);
     };
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
@@ -559,20 +565,20 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * CNT, line = e % G, i = e / G;
       const float2 chi = buf[i * LP + line];
-      const float2 p = P[i * N + line];
+      const float2 p = ldv(P, i * N + line);
       const float2 pc = cmulconj(p, chi);  // conj(P) chi
       go[q].x = fmaf(sig, pc.x, go[q].x);
       go[q].y = fmaf(sig, pc.y, go[q].y);
       // Re( conj(chi) P Osh ) = Re( conj(conj(P) chi) Osh )
       sgsum += pc.x * o[q].x + pc.y * o[q].y;
-      if (want_probe) Z[i * N + line] = cscale(cmulconj(o[q], chi), sig);
+      if (want_probe) stv(Z, i * N + line, cscale(cmulconj(o[q], chi), sig));
     }
     __syncthreads();
   }
   {
     const float s = block_sum<CNT>(sgsum, red);
     if (tid == 0)
-      jb.sg_part[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s;
+      gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s;
   }
   // Ghat = FFT_y(G_Osh): y-position derivative and adjoint y-shift
 #pragma unroll
@@ -590,15 +596,15 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
     // Re( conj(gh) * (i nu ohat) )
     dsum += nu * (gh.y * ohat[q].x - gh.x * ohat[q].y);
-    buf[i * LP + line] = cmul(gh, cconj(ry[i]));
+    buf[i * LP + line] = cmul(gh, cconj(ldv(ry, i)));
   }
   __syncthreads();
-  float2* __restrict__ GX = jb.GX + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
-  auto st_gx = [&](int line, int i, float2 v) { GX[i * N + line] = cscale(v, invN); };
+  gf2* __restrict__ GX = gmem(jb.GX) + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
+  auto st_gx = [&](int line, int i, float2 v) { stv(GX, i * N + line, cscale(v, invN)); };
   fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_gx);
   const float s = block_sum<CNT>(dsum, red);
   if (tid == 0)
-    jb.dy_part[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s * invN;
+    gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s * invN;
 }
 
 // ------------------------------------------- probe gradient: ordered k sum
@@ -607,7 +613,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
 __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const size_t plane = static_cast<size_t>(jb.N) * jb.N;
   const int nblk = static_cast<int>((plane + NT - 1) / NT);
   const int m = r.u / nblk, blk = r.u - m * nblk;
@@ -615,12 +621,12 @@ __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   if (pix >= plane) return;
   const int lm = r.l * jb.M + m;
   const size_t stride = static_cast<size_t>(jb.L) * jb.M * plane;
-  const float2* __restrict__ src = jb.Y + static_cast<size_t>(lm) * plane + pix;
-  float2* __restrict__ gp = jb.g_probe;
-  float2 acc = gp[static_cast<size_t>(lm) * plane + pix];
+  const gf2* __restrict__ src = gmem(jb.Y) + static_cast<size_t>(lm) * plane + pix;
+  gf2* __restrict__ gp = gmem(jb.g_probe);
+  float2 acc = ldv(gp, static_cast<size_t>(lm) * plane + pix);
   const int C = min(jb.C, jb.K - la.iter * jb.C);
-  for (int c = 0; c < C; ++c) acc = cadd(acc, src[c * stride]);
-  gp[static_cast<size_t>(lm) * plane + pix] = acc;
+  for (int c = 0; c < C; ++c) acc = cadd(acc, ldv(src, c * stride));
+  stv(gp, static_cast<size_t>(lm) * plane + pix, acc);
 }
 
 // -------------------------------------------------------------- row adjoint
@@ -632,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   constexpr int RB = rb_adj<N>();
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   constexpr int LP = row_lp(N);
   using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[2 * RB * LP];
@@ -640,12 +646,12 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   const int l = r.l, c = r.u, y0 = r.sub * RB;
   const int tid = threadIdx.x;
   const size_t off = (static_cast<size_t>(c) * jb.L + l) * N * N + static_cast<size_t>(y0) * N;
-  const float2* __restrict__ GXr = jb.GX + off;
-  float2* __restrict__ Xr = jb.X + off;
-  const float2* __restrict__ rx = jb.ramp + (static_cast<size_t>(c) * 2 + 1) * N;
+  const gf2* __restrict__ GXr = gmem(jb.GX) + off;
+  gf2* __restrict__ Xr = gmem(jb.X) + off;
+  const gf2* __restrict__ rx = gmem(jb.ramp) + (static_cast<size_t>(c) * 2 + 1) * N;
   const float2* __restrict__ twN = jb.tw_N;
   auto ld = [&](int line, int i) {
-    return line < RB ? GXr[line * N + i] : Xr[(line - RB) * N + i];
+    return line < RB ? ldv(GXr, line * N + i) : ldv(Xr, (line - RB) * N + i);
   };
   auto st = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = v; };
   fft_lines<N, false, 2 * RB, NT, LP, false>(buf, twN, ld, st);
@@ -656,15 +662,15 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
     const float2 xh = buf[Ix::at(line + RB, i)];
     const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
     dsum += nu * (gh.y * xh.x - gh.x * xh.y);
-    buf[Ix::at(line, i)] = cmul(gh, cconj(rx[i]));
+    buf[Ix::at(line, i)] = cmul(gh, cconj(ldv(rx, i)));
   }
   __syncthreads();
   constexpr float invN = 1.0f / N;
   auto ld1 = [&](int line, int i) { return buf[Ix::at(line, i)]; };
-  auto st1 = [&](int line, int i, float2 v) { Xr[line * N + i] = cscale(v, invN); };
+  auto st1 = [&](int line, int i, float2 v) { stv(Xr, line * N + i, cscale(v, invN)); };
   fft_lines<N, true, RB, NT, LP, false>(buf, twN, ld1, st1);
   const float s = block_sum(dsum, red);
-  if (tid == 0) jb.dx_part[(static_cast<size_t>(c) * jb.L + l) * (N / RB) + r.sub] = s * invN;
+  if (tid == 0) gmem(jb.dx_part)[(static_cast<size_t>(c) * jb.L + l) * (N / RB) + r.sub] = s * invN;
 }
 
 // ---------------------------------------------------- object gradient gather
@@ -675,7 +681,7 @@ constexpr int kTileW = 64, kTileH = 16;
 __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const int N = jb.N, l = r.l;
   const int tiles_x = (jb.W + kTileW - 1) / kTileW;
   const int ty = r.u / tiles_x, txi = r.u - ty * tiles_x;
@@ -684,32 +690,32 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   const int x = tx0 + tx;
   constexpr int PER = kTileH / (NT / kTileW);
   float2 acc[PER];
-  float2* __restrict__ G = jb.g_object + static_cast<size_t>(l) * jb.H * jb.W;
+  gf2* __restrict__ G = gmem(jb.g_object) + static_cast<size_t>(l) * jb.H * jb.W;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int y = ty0 + tyb + q * (NT / kTileW);
-    acc[q] = (x < jb.W && y < jb.H) ? G[static_cast<size_t>(y) * jb.W + x] : make_float2(0.f, 0.f);
+    acc[q] = (x < jb.W && y < jb.H) ? ldv(G, static_cast<size_t>(y) * jb.W + x) : make_float2(0.f, 0.f);
   }
   const size_t plane = static_cast<size_t>(N) * N;
   const int C = min(jb.C, jb.K - la.iter * jb.C);
   for (int c = 0; c < C; ++c) {
     int py, px;
     float dy, dx;
-    split_pos(jb.pos, la.iter * jb.C + c, py, px, dy, dx);
+    split_pos(gmem(jb.pos), la.iter * jb.C + c, py, px, dy, dx);
     if (py >= ty0 + kTileH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0) continue;
-    const float2* __restrict__ GA = jb.X + (static_cast<size_t>(c) * jb.L + l) * plane;
+    const gf2* __restrict__ GA = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * plane;
     const int xr = x - px;
     if (xr < 0 || xr >= N) continue;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int yr = ty0 + tyb + q * (NT / kTileW) - py;
-      if (yr >= 0 && yr < N) acc[q] = cadd(acc[q], GA[yr * N + xr]);
+      if (yr >= 0 && yr < N) acc[q] = cadd(acc[q], ldv(GA, yr * N + xr));
     }
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int y = ty0 + tyb + q * (NT / kTileW);
-    if (x < jb.W && y < jb.H) G[static_cast<size_t>(y) * jb.W + x] = acc[q];
+    if (x < jb.W && y < jb.H) stv(G, static_cast<size_t>(y) * jb.W + x, acc[q]);
   }
 }
 
@@ -718,29 +724,30 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
 __global__ void k_finalize_chunk(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
-  if (*jb.status) return;
+  if (*gmem(jb.status)) return;
   const int c = r.u * 64 + threadIdx.x;
   const int C = min(jb.C, jb.K - la.iter * jb.C);
   if (c >= C) return;
   const int k = la.iter * jb.C + c;
   const int n_dy = jb.N / col_group_of_dev(jb.N), n_dx = jb.N / rb_adj_dev(jb.N);
   double ls = 0.0;
-  for (int i = 0; i < jb.n_loss; ++i) ls += jb.loss_part[static_cast<size_t>(c) * jb.n_loss + i];
-  jb.loss_k[k] = ls;
+  const gf32* lp = gmem(jb.loss_part);
+  for (int i = 0; i < jb.n_loss; ++i) ls += lp[static_cast<size_t>(c) * jb.n_loss + i];
+  gmem(jb.loss_k)[k] = ls;
   if (!jb.want_adjoint) return;
   float gy = 0.f, gx = 0.f, gs = 0.f;
   for (int l = 0; l < jb.L; ++l) {
     for (int i = 0; i < n_dy; ++i) {
-      gy += jb.dy_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
-      gs += jb.sg_part[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+      gy += gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+      gs += gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
     }
-    for (int i = 0; i < n_dx; ++i) gx += jb.dx_part[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
+    for (int i = 0; i < n_dx; ++i) gx += gmem(jb.dx_part)[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
   }
   if (jb.g_pos) {
-    jb.g_pos[2 * k] = gy;
-    jb.g_pos[2 * k + 1] = gx;
+    gmem(jb.g_pos)[2 * k] = gy;
+    gmem(jb.g_pos)[2 * k + 1] = gx;
   }
-  if (jb.g_sigma) jb.g_sigma[k] = gs;
+  if (jb.g_sigma) gmem(jb.g_sigma)[k] = gs;
 }
 
 // one unit per job
@@ -748,13 +755,14 @@ __global__ void k_loss_total(Launch la, float scale) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
   if (threadIdx.x != 0) return;
-  if (*jb.status) {
-    *jb.loss = __int_as_float(0x7fc00000);
+  if (*gmem(jb.status)) {
+    *gmem(jb.loss) = __int_as_float(0x7fc00000);
     return;
   }
   double s = 0.0;
-  for (int k = 0; k < jb.K; ++k) s += jb.loss_k[k];
-  *jb.loss = static_cast<float>(s * scale);
+  const PTYCHO_GLOBAL double* lk = gmem(jb.loss_k);
+  for (int k = 0; k < jb.K; ++k) s += lk[k];
+  *gmem(jb.loss) = static_cast<float>(s * scale);
 }
 
 // Adam on real coordinates.  Segment l selects the variable (0 object,
@@ -763,10 +771,10 @@ __global__ __launch_bounds__(NT) void k_adam(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
   const int v = r.l;
-  float* __restrict__ x = jb.var_flat[v];
-  const float* __restrict__ g = jb.grad_flat[v];
-  float* __restrict__ m = jb.adam_m[v];
-  float* __restrict__ s2 = jb.adam_v[v];
+  gf32* __restrict__ x = gmem(jb.var_flat[v]);
+  const gf32* __restrict__ g = gmem(jb.grad_flat[v]);
+  gf32* __restrict__ m = gmem(jb.adam_m[v]);
+  gf32* __restrict__ s2 = gmem(jb.adam_v[v]);
   const float lr = jb.adam_lr[v];
   const long long n = jb.flat_n[v];
   const float b1 = jb.adam_beta1, b2 = jb.adam_beta2, eps = jb.adam_eps;
