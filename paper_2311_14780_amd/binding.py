@@ -208,6 +208,21 @@ def ptycho_workspace_bytes(problems: Sequence[Problem], which: int = 1, chunk: i
     return int(out.value)
 
 
+def workspace_bytes_for_shapes(shapes: Sequence[tuple], which: int = 1, chunk: int = 0) -> int:
+    """Workspace bytes for jobs given only by their sizes
+    (K, L, M, N, H, W, pads), without resampling tables."""
+    arr = (JobT * len(shapes))()
+    for i, (K, L, M, N, H, W, pads) in enumerate(shapes):
+        arr[i].K, arr[i].L, arr[i].M, arr[i].N, arr[i].H, arr[i].W = K, L, M, N, H, W
+        for l, p in enumerate(pads):
+            arr[i].pad[l] = int(p)
+    out = ctypes.c_size_t(0)
+    code = lib().ptycho_workspace_bytes(arr, len(shapes), int(which), int(chunk), ctypes.byref(out))
+    if code:
+        raise PtychoError(code, "ptycho_workspace_bytes")
+    return int(out.value)
+
+
 def ptycho_forward(problems: Sequence[Problem], intensities: Sequence[torch.Tensor],
                    workspace: torch.Tensor, stream=None) -> None:
     outs = (_c_p * len(problems))(*[t.data_ptr() for t in intensities])

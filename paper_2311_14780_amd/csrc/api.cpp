@@ -175,7 +175,8 @@ namespace {
 
 bool has_resample(const ptycho_job_t& j) { return j.rs_idx != nullptr; }
 
-int validate_job(const ptycho_job_t& j, bool need_measured) {
+// check_ptrs = false: only sizes are validated (workspace queries).
+int validate_job(const ptycho_job_t& j, bool need_measured, bool check_ptrs = true) {
   if (j.K < 0 || j.L < 1 || j.L > PTYCHO_MAX_WAVELENGTHS || j.M < 1 || j.M > PTYCHO_MAX_MODES ||
       j.N < 1 || j.H < 1 || j.W < 1)
     return PTYCHO_EINVAL;
@@ -188,9 +189,11 @@ int validate_job(const ptycho_job_t& j, bool need_measured) {
     if (j.pad[l] < j.N) return PTYCHO_ERANGE;
     if (!supported(j.N, j.pad[l])) return PTYCHO_EUNSUPPORTED;
   }
-  if (!j.object || !j.probe) return PTYCHO_EINVAL;
-  if (j.K > 0 && !j.pos) return PTYCHO_EINVAL;
-  if (need_measured && j.K > 0 && !j.measured) return PTYCHO_EINVAL;
+  if (check_ptrs) {
+    if (!j.object || !j.probe) return PTYCHO_EINVAL;
+    if (j.K > 0 && !j.pos) return PTYCHO_EINVAL;
+    if (need_measured && j.K > 0 && !j.measured) return PTYCHO_EINVAL;
+  }
   const int nrs = (j.rs_idx != nullptr) + (j.rs_w != nullptr) + (j.rsT_ptr != nullptr) +
                   (j.rsT_col != nullptr) + (j.rsT_val != nullptr);
   if (nrs != 0 && nrs != 5) return PTYCHO_EINVAL;
@@ -665,7 +668,7 @@ int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t
                                int32_t chunk, size_t* bytes) {
   if (!bytes || !jobs || n_jobs < 1 || which < 0 || which > 2) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i) {
-    const int e = validate_job(jobs[i], false);
+    const int e = validate_job(jobs[i], false, false);
     if (e) return e;
   }
   // chunk region: the largest group needs its jobs' chunks side by side

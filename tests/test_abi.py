@@ -6,6 +6,7 @@ import re
 import subprocess
 
 import numpy as np
+import synth
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -92,16 +93,14 @@ def test_invalid_jobs_rejected_on_host(change, code):
 
 
 def test_null_pointers_rejected():
-    j = _job()
-    j.object = None
-    assert _ws_bytes(j)[0] == B.PTYCHO_EINVAL
-    j = _job()
-    j.measured = None
     loss = B.LossT(0, 1e-6, 1.0)
     grads = B.GradsT()
-    rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
-                                  ctypes.c_void_p(0x2000), 1 << 20, None)
-    assert rc == B.PTYCHO_EINVAL
+    for field in ("object", "probe", "pos", "measured"):
+        j = _job()
+        setattr(j, field, None)
+        rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                                      ctypes.c_void_p(0x2000), 1 << 20, None)
+        assert rc == B.PTYCHO_EINVAL, field
     rc = B.lib().ptycho_loss_grad(None, 1, ctypes.byref(loss), ctypes.byref(grads),
                                   ctypes.c_void_p(0x2000), 1 << 20, None)
     assert rc == B.PTYCHO_EINVAL
@@ -138,3 +137,22 @@ def test_transpose_table_rejects_bad_index():
     w = np.full((1, 4), 0.25, np.float32)
     with pytest.raises(B.PtychoError):
         B.ptycho_transpose_table(idx, w, 4)
+
+
+def test_workspace_query_reads_sizes_only():
+    """A scheduler sizes a call before allocating: the query ignores the
+    array pointers and gives the same answer as with them."""
+    j = _job()
+    ref = _ws_bytes(j, which=2, chunk=3)
+    for field in ("object", "probe", "pos", "measured"):
+        setattr(j, field, None)
+    assert _ws_bytes(j, which=2, chunk=3) == ref
+    got = B.workspace_bytes_for_shapes([(4, 2, 3, 64, 128, 128, (64, 80))], which=2, chunk=3)
+    assert ref == (0, got)
+
+
+def test_serving_mix_pads_are_compiled_in():
+    import synth.serving as SS
+    for w in SS.serving_jobs(64, 4):
+        for p in synth.pads_for(w.N, w.harmonics, w.ref_harmonic):
+            assert B.ptycho_supported(w.N, p), (w.N, p)
