@@ -16,11 +16,19 @@ is one (position, wavelength, probe mode) propagation, forward and adjoint).
 ``roofline`` reports the kernel class with the largest GPU time: algorithmic
 HBM bytes per launch / average launch duration (HIP events on the launch
 stream, over the timed region) against the 8 TB/s HBM3E peak.
+``roofline.traffic`` is the measured HBM traffic per launch of that kernel
+(rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain-copy
+calibration; committed under profiles/), reported only while the kernel
+sources are the ones that were measured, else null.
 ``cpu_baseline`` times the FP64 oracle on a bounded sample of positions.
+``serving`` runs a reduced serving stream (continuous batching against
+first-come first-served sequential execution); ``--serving-jobs 64
+--serving-iters 50`` is the full stream.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -65,6 +73,24 @@ def alg_bytes(kernel: str, K: int, L: int, M: int, N: int, H: int, W: int) -> fl
 def step_alg_bytes(K, L, M, N, H, W) -> float:
     return sum(alg_bytes(k, K, L, M, N, H, W) for k in
                ("row_fwd", "col_fwd", "det", "col_adj", "row_adj", "obj_gather", "probe_reduce", "adam"))
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary, if the kernel
+    sources still hash to the measured ones; else None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_step_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2311_14780_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("kernels.hip", "fft.hpp", "kernels.hpp"))
+    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+        return None
+    k = d["kernels"].get(kernel)
+    if not k:
+        return None
+    return float(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
 
 
 def build_inputs(w, device):
@@ -127,6 +153,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=16)
+    ap.add_argument("--serving-iters", type=int, default=5)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -191,8 +220,11 @@ def main(argv=None):
         d = kern_out[dom]
         per_launch = alg_bytes(dom, K, L, M, N, H, W) / d["launches_per_step"]
         achieved = per_launch / (d["avg_launch_us"] * 1e-6) / 1e9
+        traffic = measured_traffic(w.name, dom)
         roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic / 1e9, 4),
+                    traffic_unit="GB per launch",
                     alg_bytes_per_launch=per_launch, avg_launch_us=round(d["avg_launch_us"], 2))
         for name, d in kern_out.items():
             b = alg_bytes(name, K, L, M, N, H, W)
@@ -201,6 +233,14 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, truth, start)
+    serving = None
+    pads = list(prob.pads)
+    if not args.no_serving:
+        from paper_2311_14780_amd import serving as S
+        del g, adam, ws, prob
+        torch.cuda.empty_cache()
+        serving = S.run_stream(args.serving_jobs, args.serving_iters,
+                               log=lambda m: print(m, file=sys.stderr, flush=True))
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pattern-modes/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -208,15 +248,16 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"{w.name}: {L} wavelengths (harmonics {'/'.join(map(str, w.harmonics))}) "
                                 f"x {M} probe modes, probe {N}x{N}, object {H}x{W} per wavelength, "
-                                f"{K} positions ({w.scan}), pads {'/'.join(map(str, prob.pads))}, "
+                                f"{K} positions ({w.scan}), pads {'/'.join(map(str, pads))}, "
                                 f"{w.photons:.0e} photons/pattern; step = loss + gradients + Adam"),
-                   "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": list(prob.pads),
+                   "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": pads,
                    "parallelism": "single GPU"},
         "step_roofline": {"alg_bytes_per_step": b_step,
                           "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),
                           "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
         "kernels": kern_out,
     }
     print(json.dumps(out))
