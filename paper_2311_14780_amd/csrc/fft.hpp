@@ -352,12 +352,45 @@ struct Lds {
 // entries w_{Ns R}^{r k} (forward sign) stored as [k][r - 1], k < Ns,
 // 1 <= r < R; passes are concatenated in plan order.
 
+// Twiddles of one pass for this thread's butterflies, [iteration][r - 1].
+template <int n, int R, int LINES, int NT>
+struct PassTw {
+  static constexpr int NB = n / R;
+  static constexpr int BF = LINES * NB;
+  static constexpr int ITER = (BF + NT - 1) / NT;
+  float2 w[ITER][R > 1 ? R - 1 : 1];
+};
+
+// Issues the loads of the twiddles of pass (R, Ns, TOFF) for this thread.
+template <int n, int R, int Ns, int TOFF, int LINES, int NT, bool LINE_FAST, class Tw>
+__device__ __forceinline__ void load_pass_tw(Tw tw, PassTw<n, R, LINES, NT>& out) {
+  if constexpr (Ns > 1) {
+    using P = PassTw<n, R, LINES, NT>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < P::ITER; ++it) {
+      const int b = tid + it * NT;
+      if ((P::BF % NT == 0) || b < P::BF) {
+        const int j = LINE_FAST ? (b / LINES) : (b % P::NB);
+        // one address, constant offsets: the R - 1 values are contiguous
+        const auto t = tw + TOFF + (j % Ns) * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) out.w[it][r - 1] = ldv(t, r - 1);
+      }
+    }
+  }
+}
+
 // One Stockham pass.  FIRST: inputs from `load(line, i)`; otherwise from LDS.
-// LAST: outputs to `store(line, i, v)`; otherwise to LDS.  TOFF: offset of
-// this pass's twiddles in the table.
-template <int n, int R, int Ns, int TOFF, bool FIRST, bool LAST, bool INV, int LINES, int NT,
-          int LP, bool LINE_FAST, class Buf, class Tw, class Load, class Store>
-__device__ __forceinline__ void stockham_pass(Buf buf, Tw tw, const Load& load, const Store& store) {
+// LAST: outputs to `store(line, i, v)`; otherwise to LDS.  `wcur` holds this
+// pass's twiddles, loaded during the previous pass; `prefetch()` issues the
+// next pass's twiddle loads once this pass's reads are done, so that they
+// are in flight across the barrier and the write phase.
+template <int n, int R, int Ns, bool FIRST, bool LAST, bool INV, int LINES, int NT, int LP,
+          bool LINE_FAST, class Buf, class Load, class Store, class Prefetch>
+__device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES, NT>& wcur,
+                                              const Load& load, const Store& store,
+                                              const Prefetch& prefetch) {
   constexpr int NB = n / R;             // butterflies per line
   constexpr int BF = LINES * NB;        // butterflies per pass
   constexpr int ITER = (BF + NT - 1) / NT;
@@ -375,30 +408,21 @@ __device__ __forceinline__ void stockham_pass(Buf buf, Tw tw, const Load& load, 
     if ((BF % NT == 0) || b < BF) {
       const int line = LINE_FAST ? (b % LINES) : (b / NB);
       const int j = LINE_FAST ? (b / LINES) : (b % NB);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
       if (Ns > 1) {
-        // issue the twiddle loads first: one address, constant offsets
-        const int k = j % Ns;
-        const auto t = tw + TOFF + k * (R - 1);
-        float2 w[R - 1];
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[r - 1] = ldv(t, r - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 ww = w[r - 1];
+          float2 ww = wcur.w[it][r - 1];
           if (INV) ww.y = -ww.y;
           v[it][r] = cmul(v[it][r], ww);
         }
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
       }
       Dft<R, INV>::run(v[it]);
     }
   }
+  prefetch();
   __syncthreads();  // every read of this pass precedes any write (in-place LDS)
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
@@ -419,16 +443,36 @@ __device__ __forceinline__ void stockham_pass(Buf buf, Tw tw, const Load& load, 
   __syncthreads();
 }
 
+template <int R, int... Rest>
+struct FirstRadix {
+  static constexpr int value = R;
+};
+template <class P>
+struct FirstRadixOf;
+template <int... Rs>
+struct FirstRadixOf<Radices<Rs...>> {
+  static constexpr int value = FirstRadix<Rs...>::value;
+};
+
 template <int n, int Ns, int TOFF, bool FIRST, bool INV, int LINES, int NT, int LP, bool LINE_FAST,
           class Buf, class Tw, class Load, class Store, int R, int... Rest>
-__device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const Load& load, const Store& store,
+__device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const PassTw<n, R, LINES, NT>& wcur,
+                                             const Load& load, const Store& store,
                                              Radices<R, Rest...>) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  stockham_pass<n, R, Ns, TOFF, FIRST, LAST, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store);
-  if constexpr (!LAST) {
+  if constexpr (LAST) {
+    stockham_pass<n, R, Ns, FIRST, true, INV, LINES, NT, LP, LINE_FAST>(buf, wcur, load, store,
+                                                                          [] {});
+  } else {
     constexpr int NEXT_TOFF = TOFF + (Ns > 1 ? Ns * (R - 1) : 0);
-    stockham_run<n, Ns * R, NEXT_TOFF, false, INV, LINES, NT, LP, LINE_FAST>(buf, tw, load, store,
-                                                                              Radices<Rest...>{});
+    constexpr int R2 = FirstRadix<Rest...>::value;
+    PassTw<n, R2, LINES, NT> wnext;
+    stockham_pass<n, R, Ns, FIRST, false, INV, LINES, NT, LP, LINE_FAST>(
+        buf, wcur, load, store, [&] {
+          load_pass_tw<n, R2, Ns * R, NEXT_TOFF, LINES, NT, LINE_FAST>(tw, wnext);
+        });
+    stockham_run<n, Ns * R, NEXT_TOFF, false, INV, LINES, NT, LP, LINE_FAST>(
+        buf, tw, wnext, load, store, Radices<Rest...>{});
   }
 }
 
@@ -449,8 +493,9 @@ __device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, cons
   unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
   asm volatile("" : "+s"(lo), "+s"(hi));
   const gf2* tg = reinterpret_cast<const gf2*>((static_cast<unsigned long long>(hi) << 32) | lo);
-  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, load, store,
-                                                              typename Plan<n>::type{});
+  using Plan0 = typename Plan<n>::type;
+  PassTw<n, FirstRadixOf<Plan0>::value, LINES, NT> w0;  // the first pass has no twiddles
+  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, w0, load, store, Plan0{});
 }
 
 }  // namespace ptycho
