@@ -352,13 +352,20 @@ struct Lds {
 // entries w_{Ns R}^{r k} (forward sign) stored as [k][r - 1], k < Ns,
 // 1 <= r < R; passes are concatenated in plan order.
 
+// Twiddles loaded per butterfly: w and w^2 (one 16-byte load); the higher
+// powers are products w^r = w^(r/2) w^(r - r/2) (at most a few roundings).
+// Loading all R - 1 values per thread made the twiddle reads the largest
+// stream through the L1 cache (every thread reads its own copy).
+constexpr int kTwLoaded = 2;
+
 // Twiddles of one pass for this thread's butterflies, [iteration][r - 1].
 template <int n, int R, int LINES, int NT>
 struct PassTw {
   static constexpr int NB = n / R;
   static constexpr int BF = LINES * NB;
   static constexpr int ITER = (BF + NT - 1) / NT;
-  float2 w[ITER][R > 1 ? R - 1 : 1];
+  static constexpr int Q = R - 1 < kTwLoaded ? R - 1 : kTwLoaded;
+  float2 w[ITER][Q > 0 ? Q : 1];
 };
 
 // Issues the loads of the twiddles of pass (R, Ns, TOFF) for this thread.
@@ -372,10 +379,10 @@ __device__ __forceinline__ void load_pass_tw(Tw tw, PassTw<n, R, LINES, NT>& out
       const int b = tid + it * NT;
       if ((P::BF % NT == 0) || b < P::BF) {
         const int j = LINE_FAST ? (b / LINES) : (b % P::NB);
-        // one address, constant offsets: the R - 1 values are contiguous
+        // one address, constant offsets: the values are contiguous
         const auto t = tw + TOFF + (j % Ns) * (R - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) out.w[it][r - 1] = ldv(t, r - 1);
+        for (int r = 1; r <= P::Q; ++r) out.w[it][r - 1] = ldv(t, r - 1);
       }
     }
   }
@@ -412,9 +419,13 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
       for (int r = 0; r < R; ++r)
         v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
       if (Ns > 1) {
+        constexpr int Q = PassTw<n, R, LINES, NT>::Q;
+        float2 wr[R];
+#pragma unroll
+        for (int r = 1; r < R; ++r) wr[r] = r <= Q ? wcur.w[it][r - 1] : cmul(wr[r / 2], wr[r - r / 2]);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 ww = wcur.w[it][r - 1];
+          float2 ww = wr[r];
           if (INV) ww.y = -ww.y;
           v[it][r] = cmul(v[it][r], ww);
         }
