@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ptycho {
 
 // Address-space qualified pointers.  Pointers that reach a kernel through
@@ -352,6 +354,51 @@ struct Lds {
 // entries w_{Ns R}^{r k} (forward sign) stored as [k][r - 1], k < Ns,
 // 1 <= r < R; passes are concatenated in plan order.
 
+template <int R, int... Rest>
+struct FirstRadix {
+  static constexpr int value = R;
+};
+template <class P>
+struct FirstRadixOf;
+template <int... Rs>
+struct FirstRadixOf<Radices<Rs...>> {
+  static constexpr int value = FirstRadix<Rs...>::value;
+};
+
+// Inputs of the first pass of an FFT, loaded ahead of time with
+// fft_first_load and handed to fft_lines in place of a load functor, so that
+// the loads of the next transform are in flight during the current one.
+template <int n, int LINES, int NT, bool LINE_FAST>
+struct PreIn {
+  static constexpr int R = FirstRadixOf<typename Plan<n>::type>::value;
+  static constexpr int NB = n / R;
+  static constexpr int BF = LINES * NB;
+  static constexpr int ITER = (BF + NT - 1) / NT;
+  float2 v[ITER][R];
+};
+template <class T>
+struct IsPreIn : std::false_type {};
+template <int n, int LINES, int NT, bool LF>
+struct IsPreIn<PreIn<n, LINES, NT, LF>> : std::true_type {};
+
+// Issues the first-pass loads of an FFT: in.v[it][r] = load(line, j + r NB).
+template <int n, int LINES, int NT, bool LINE_FAST, class Load>
+__device__ __forceinline__ void fft_first_load(PreIn<n, LINES, NT, LINE_FAST>& in,
+                                               const Load& load) {
+  using P = PreIn<n, LINES, NT, LINE_FAST>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < P::ITER; ++it) {
+    const int b = tid + it * NT;
+    if ((P::BF % NT == 0) || b < P::BF) {
+      const int line = LINE_FAST ? (b % LINES) : (b / P::NB);
+      const int j = LINE_FAST ? (b / LINES) : (b % P::NB);
+#pragma unroll
+      for (int r = 0; r < P::R; ++r) in.v[it][r] = load(line, j + r * P::NB);
+    }
+  }
+}
+
 // Twiddles loaded per butterfly: w and w^2 (one 16-byte load); the higher
 // powers are products w^r = w^(r/2) w^(r - r/2) (at most a few roundings).
 // Loading all R - 1 values per thread made the twiddle reads the largest
@@ -416,8 +463,14 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
       const int line = LINE_FAST ? (b % LINES) : (b / NB);
       const int j = LINE_FAST ? (b / LINES) : (b % NB);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        v[it][r] = FIRST ? load(line, j + r * NB) : ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
+      for (int r = 0; r < R; ++r) {
+        if constexpr (!FIRST)
+          v[it][r] = ldv(buf, Ix::template at_r<NB, RD_MODE>(line, j, r));
+        else if constexpr (IsPreIn<Load>::value)
+          v[it][r] = load.v[it][r];
+        else
+          v[it][r] = load(line, j + r * NB);
+      }
       if (Ns > 1) {
         constexpr int Q = PassTw<n, R, LINES, NT>::Q;
         float2 wr[R];
@@ -454,16 +507,6 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
   __syncthreads();
 }
 
-template <int R, int... Rest>
-struct FirstRadix {
-  static constexpr int value = R;
-};
-template <class P>
-struct FirstRadixOf;
-template <int... Rs>
-struct FirstRadixOf<Radices<Rs...>> {
-  static constexpr int value = FirstRadix<Rs...>::value;
-};
 
 template <int n, int Ns, int TOFF, bool FIRST, bool INV, int LINES, int NT, int LP, bool LINE_FAST,
           class Buf, class Tw, class Load, class Store, int R, int... Rest>

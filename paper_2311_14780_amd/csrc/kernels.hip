@@ -549,18 +549,28 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
 
   const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
-  for (int m = 0; m < jb.M; ++m) {
-    gf2* __restrict__ Z = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
-    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
-    auto ld_z = [&](int line, int t) {
+  gf2* __restrict__ Z0 = gmem(jb.Y) + (static_cast<size_t>(c) * jb.L + l) * jb.M * N * N + x0;
+  // the first-pass inputs of mode m + 1 are loaded while mode m is processed
+  using ZIn = PreIn<NL, G, CNT, true>;
+  auto zload = [&](int m, ZIn& zin) {
+    const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
+    fft_first_load(zin, [&](int line, int t) {
       int u = t + N / 2;
       if (u >= NL) u -= NL;
-      return u < N ? ldv(Z, u * N + line) : make_float2(0.f, 0.f);
-    };
+      return u < N ? ldv(Zm, u * N + line) : make_float2(0.f, 0.f);
+    });
+  };
+  ZIn zcur;
+  zload(0, zcur);
+  for (int m = 0; m < jb.M; ++m) {
+    gf2* __restrict__ Z = Z0 + static_cast<size_t>(m) * N * N;
+    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
+    ZIn znext;
+    if (m + 1 < jb.M) zload(m + 1, znext);
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
     };
-    fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_z, st_chi);
+    fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * CNT, line = e % G, i = e / G;
@@ -574,6 +584,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
       if (want_probe) stv(Z, i * N + line, cscale(cmulconj(o[q], chi), sig));
     }
     __syncthreads();
+    zcur = znext;
   }
   {
     const float s = block_sum<CNT>(sgsum, red);
