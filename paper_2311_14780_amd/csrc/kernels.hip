@@ -687,18 +687,25 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
 // ---------------------------------------------------- object gradient gather
 // Tile of 16 x 64 object pixels; every window of the chunk that overlaps the
 // tile adds its G_A values in ascending k.  No atomics: each pixel has one
-// owner thread, so the sum order is fixed.  units: (l, tile)
+// owner thread, so the sum order is fixed.  The block first tests the
+// chunk's windows in parallel and compacts the overlapping ones, in
+// ascending order, into an LDS list (wave ballots), then accumulates over
+// that list only.  units: (l, tile)
 constexpr int kTileW = 64, kTileH = 16;
+constexpr int kListMax = 1024;  // windows tested per round
 __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
+  __shared__ int list_c[kListMax], list_py[kListMax], list_px[kListMax];
+  __shared__ int wave_cnt[NT / 64];
   const int N = jb.N, l = r.l;
   const int tiles_x = (jb.W + kTileW - 1) / kTileW;
   const int ty = r.u / tiles_x, txi = r.u - ty * tiles_x;
   const int tx0 = txi * kTileW, ty0 = ty * kTileH;
   const int tx = threadIdx.x % kTileW, tyb = threadIdx.x / kTileW;  // tyb in [0, 4)
   const int x = tx0 + tx;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int PER = kTileH / (NT / kTileW);
   float2 acc[PER];
   gf2* __restrict__ G = gmem(jb.g_object) + static_cast<size_t>(l) * jb.H * jb.W;
@@ -709,19 +716,51 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   }
   const size_t plane = static_cast<size_t>(N) * N;
   const int C = min(jb.C, jb.K - la.iter * jb.C);
-  for (int c = 0; c < C; ++c) {
-    int py, px;
-    float dy, dx;
-    split_pos(gmem(jb.pos), la.iter * jb.C + c, py, px, dy, dx);
-    if (py >= ty0 + kTileH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0) continue;
-    const gf2* __restrict__ GA = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * plane;
-    const int xr = x - px;
-    if (xr < 0 || xr >= N) continue;
+  const int kbase = la.iter * jb.C;
+  const gf32* __restrict__ pos = gmem(jb.pos);
+  for (int c0 = 0; c0 < C; c0 += kListMax) {
+    const int cn = min(kListMax, C - c0);
+    int count = 0;  // block-uniform
+    for (int s0 = 0; s0 < cn; s0 += NT) {
+      const int c = c0 + s0 + threadIdx.x;
+      bool hit = false;
+      int py = 0, px = 0;
+      if (s0 + threadIdx.x < cn) {
+        float dy, dx;
+        split_pos(pos, kbase + c, py, px, dy, dx);
+        hit = !(py >= ty0 + kTileH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0);
+      }
+      const unsigned long long m = __ballot(hit);
+      if (lane == 0) wave_cnt[wid] = __popcll(m);
+      __syncthreads();
+      int before = 0, total = 0;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int yr = ty0 + tyb + q * (NT / kTileW) - py;
-      if (yr >= 0 && yr < N) acc[q] = cadd(acc[q], ldv(GA, yr * N + xr));
+      for (int w = 0; w < NT / 64; ++w) {
+        const int n = wave_cnt[w];
+        before += w < wid ? n : 0;
+        total += n;
+      }
+      if (hit) {
+        const int idx = count + before + __popcll(m & ((1ull << lane) - 1ull));
+        list_c[idx] = c;
+        list_py[idx] = py;
+        list_px[idx] = px;
+      }
+      count += total;
+      __syncthreads();  // wave_cnt is rewritten next round; the list is complete
     }
+    for (int i = 0; i < count; ++i) {
+      const int c = list_c[i], py = list_py[i], px = list_px[i];
+      const gf2* __restrict__ GA = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * plane;
+      const int xr = x - px;
+      if (xr < 0 || xr >= N) continue;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int yr = ty0 + tyb + q * (NT / kTileW) - py;
+        if (yr >= 0 && yr < N) acc[q] = cadd(acc[q], ldv(GA, yr * N + xr));
+      }
+    }
+    __syncthreads();  // the list is rebuilt for the next round
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
