@@ -141,3 +141,30 @@ def sample_counts(intensity: np.ndarray, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed + 2000))
     lam = np.maximum(np.asarray(intensity, dtype=np.float64), 0.0)
     return rng.poisson(lam).astype(np.float32)
+
+
+def synthetic_counts(K: int, N: int, photons: float, seed: int, n_base: int = 16) -> np.ndarray:
+    """Poisson photon counts with a workload's photon budget but no model
+    behind them, float32 [K][N][N].
+
+    ``n_base`` patterns (a bright centre on a smooth positive field, scaled
+    to ``photons`` in total) are drawn once; position k gets pattern
+    k mod n_base, shifted along x by k // n_base pixels.  Meant for tests at
+    full size, where computing every position's pattern from a model would
+    take too long; any fixed data serve for comparing two implementations of
+    the same loss.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed + 3000))
+    yy, xx = np.mgrid[0:N, 0:N].astype(np.float64)
+    r2 = (yy - N / 2.0) ** 2 + (xx - N / 2.0) ** 2
+    centre = 50.0 * np.exp(-r2 / (0.05 * N) ** 2)
+    base = []
+    for _ in range(n_base):
+        f = gaussian_filter(rng.normal(size=(N, N)), 3.0, mode="wrap")
+        lam = np.exp(f / max(f.std(), 1e-30)) + centre
+        lam *= photons / lam.sum()
+        base.append(rng.poisson(lam).astype(np.float32))
+    out = np.empty((K, N, N), dtype=np.float32)
+    for k in range(K):
+        out[k] = np.roll(base[k % n_base], (k // n_base) % N, axis=1)
+    return out
