@@ -139,7 +139,10 @@ int32_t ptycho_supported(int32_t N, int32_t pad);
 /* Workspace bytes needed to run `which` (0 forward, 1 loss+gradient, 2 step)
    for these jobs with at most `chunk` positions per pass (chunk <= 0: all K).
    Any workspace of at least the chunk = 1 size works; a larger workspace
-   lets the library process more positions per launch.  Only the size fields
+   lets the library process more positions per launch.  Loss + gradient
+   calls process the positions of a job in groups of up to 4 (the probe
+   gradient of a group is summed in on-chip memory), so for them `chunk` is
+   rounded up to a multiple of the job's group size.  Only the size fields
    (K, L, M, N, H, W, pad) and whether rs_idx is non-NULL are read: the array
    pointers may be NULL, so a scheduler can size a call before allocating. */
 int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t which,

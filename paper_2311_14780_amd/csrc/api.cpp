@@ -261,8 +261,29 @@ struct Call {
   char* chunk_base = nullptr;
   size_t chunk_bytes = 0;
   std::vector<JobDev> host_jobs;
-  std::vector<int> chunk;  // C per job
+  std::vector<int> chunk;   // C per job
+  std::vector<int> pgroup;  // probe-gradient group size per job
 };
+
+int max_pad(const ptycho_job_t& j) {
+  int m = j.N;
+  for (int l = 0; l < j.L; ++l) m = std::max(m, j.pad[l]);
+  return m;
+}
+
+// Positions whose probe-gradient terms are summed in one column-adjoint
+// block (a function of the job alone, so results do not depend on the
+// other jobs of a call).
+int job_probe_group(const ptycho_job_t& j, bool want_probe) {
+  return want_probe ? probe_group_of(j.N, j.M, max_pad(j)) : 1;
+}
+
+// Chunk sizes are multiples of the group size (except a chunk holding the
+// whole scan), so that groups never straddle chunks.
+int round_chunk(int C, int K, int group) {
+  if (group <= 1 || C >= K) return std::min(C, std::max(K, 1));
+  return std::min(K, (C + group - 1) / group * group);
+}
 
 bool wants_adjoint(const Call& c, int i) {
   if (c.which == 0) return false;
@@ -301,12 +322,15 @@ int plan_chunks(Call& c, const std::vector<int>& members, int* iters) {
     return PTYCHO_OK;
   }
   const int w = c.which == 0 ? 0 : 1;
+  auto chunk_of = [&](int i, int T) {
+    const int K = c.jobs[i].K;
+    return round_chunk((K + T - 1) / T, K, c.pgroup[i]);
+  };
   auto need = [&](int T) {
     size_t b = 0;
     for (int i : members) {
-      const int K = c.jobs[i].K;
-      if (K == 0) continue;
-      b += per_position_bytes(c.jobs[i], w) * static_cast<size_t>((K + T - 1) / T);
+      if (c.jobs[i].K == 0) continue;
+      b += per_position_bytes(c.jobs[i], w) * static_cast<size_t>(chunk_of(i, T));
     }
     return b;
   };
@@ -317,10 +341,7 @@ int plan_chunks(Call& c, const std::vector<int>& members, int* iters) {
     if (need(mid) <= c.chunk_bytes) hi = mid; else lo = mid + 1;
   }
   int T = lo;
-  for (int i : members) {
-    const int K = c.jobs[i].K;
-    c.chunk[i] = K == 0 ? 1 : (K + T - 1) / T;
-  }
+  for (int i : members) c.chunk[i] = c.jobs[i].K == 0 ? 1 : chunk_of(i, T);
   // iterations actually needed with these chunk sizes
   int it = 0;
   for (int i : members) {
@@ -407,6 +428,7 @@ void fill_job(Call& c, int i, char** cursor) {
   d.C = C;
   d.n_loss = n_loss_of(j);
   d.want_adjoint = wants_adjoint(c, i) ? 1 : 0;
+  d.probe_group = c.pgroup[i];
   if (c.adam) {
     const ptycho_adam_t& a = c.adam[i];
     d.adam_m[0] = a.m_object;
@@ -530,9 +552,11 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
   if (key.adjoint) {
     for (size_t p = 0; p < nls.size(); ++p) {
       cola[p] = ph.begin();
-      for (size_t q = 0; q < members.size(); ++q)
+      for (size_t q = 0; q < members.size(); ++q) {
+        const int pg = c.pgroup[members[q]];
         for (int l = 0; l < c.jobs[members[q]].L; ++l)
-          if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(cola[p], members[q], l, cnt[q]);
+          if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
+      }
     }
     prob = ph.begin();
     const long long nblk = static_cast<long long>((plane + 255) / 256);
@@ -581,8 +605,20 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     }
   }
   if (key.adjoint) {
-    for (size_t p = 0; p < nls.size(); ++p)
-      LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, s));
+    for (size_t p = 0; p < nls.size(); ++p) {
+      size_t lds = 0;  // the launch's largest probe-gradient accumulator
+      bool grouped = false;
+      for (size_t q = 0; q < members.size(); ++q) {
+        const ptycho_job_t& j = c.jobs[members[q]];
+        bool uses = false;
+        for (int l = 0; l < j.L; ++l) uses |= j.pad[l] == nls[p];
+        if (!uses || !cnt[q]) continue;
+        grouped |= c.pgroup[members[q]] > 1;
+        lds = std::max(lds, col_adj_lds_of(N, j.M, c.pgroup[members[q]]));
+      }
+      LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
+                                        grouped, s));
+    }
     LAUNCH(KC_PROBE_REDUCE, launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
     LAUNCH(KC_ROW_ADJ, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));
     LAUNCH(KC_OBJ_GATHER, launch_simple(KObjGather, launch_of(c, obj, iter), obj.units, s));
@@ -623,6 +659,9 @@ int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
   for (int i = 0; i < c.n; ++i)
     groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i)}].push_back(i);
   c.chunk.assign(c.n, 1);
+  c.pgroup.assign(c.n, 1);
+  for (int i = 0; i < c.n; ++i)
+    c.pgroup[i] = job_probe_group(c.jobs[i], wants_adjoint(c, i) && c.grads[i].g_probe != nullptr);
   std::map<GroupKey, int> iters;
   for (auto& kv : groups) {
     int it = 0;
@@ -675,7 +714,9 @@ int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t
   std::map<std::tuple<int, bool>, size_t> group_bytes;
   for (int i = 0; i < n_jobs; ++i) {
     const int K = jobs[i].K;
-    const int c = chunk <= 0 ? std::max(K, 1) : std::max(1, std::min<int>(chunk, std::max(K, 1)));
+    int c = chunk <= 0 ? std::max(K, 1) : std::max(1, std::min<int>(chunk, std::max(K, 1)));
+    // a loss + gradient call may group positions for the probe gradient
+    if (which != 0) c = std::max(1, round_chunk(c, K, job_probe_group(jobs[i], true)));
     group_bytes[std::make_tuple(jobs[i].N, has_resample(jobs[i]))] +=
         per_position_bytes(jobs[i], which == 0 ? 0 : 1) * static_cast<size_t>(c);
   }

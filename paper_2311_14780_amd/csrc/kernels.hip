@@ -505,8 +505,15 @@ __global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
 }
 
 // ---------------------------------------------------------- column adjoint
-// units: (l, c) for the wavelengths whose DFT size is NL
-template <int N, int NL>
+// units: (l, group of jb.probe_group positions) for the wavelengths whose DFT
+// size is NL.  A block takes its group's positions in ascending order; with
+// groups of more than one position the probe-gradient terms of the group
+// are summed in LDS (pacc, [M][N][G], dynamic shared memory) and written once,
+// into the slot of the group's first position.  GROUPED = false is the
+// instance for launches whose jobs all have groups of one: one position per
+// block, and the columns of mode m + 1 are loaded while mode m is processed
+// (too many registers on top of the group loop).
+template <int N, int NL, bool GROUPED>
 __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   constexpr int G = col_group<N>();
   const UnitRef r = decode<N / G>(la);
@@ -517,8 +524,18 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   constexpr int NE = N * G / CNT;
   __shared__ float2 buf[NL * LP];
   __shared__ float red[CNT / 64];
-  const int l = r.l, c = r.u, k = la.iter * jb.C + c, x0 = r.sub * G;
+  extern __shared__ float2 pacc[];
+  const int l = r.l, x0 = r.sub * G;
   const int tid = threadIdx.x;
+  const int PG = GROUPED ? jb.probe_group : 1;
+  const bool group_acc = GROUPED && want_probe && PG > 1;
+  const int cbeg = r.u * PG;
+  const int cend = min(cbeg + PG, min(jb.C, jb.K - la.iter * jb.C));
+  if (group_acc)
+    for (int e = tid; e < jb.M * N * G; e += CNT) pacc[e] = make_float2(0.f, 0.f);
+  // (the transforms below synchronise the block before pacc is first used)
+  for (int c = cbeg; c < cend; ++c) {
+  const int k = la.iter * jb.C + c;
   const gf2* __restrict__ X = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
   const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
   const float2* __restrict__ twN = jb.tw_N;
@@ -550,7 +567,6 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
   gf2* __restrict__ Z0 = gmem(jb.Y) + (static_cast<size_t>(c) * jb.L + l) * jb.M * N * N + x0;
-  // the first-pass inputs of mode m + 1 are loaded while mode m is processed
   using ZIn = PreIn<NL, G, CNT, true>;
   auto zload = [&](int m, ZIn& zin) {
     const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
@@ -561,16 +577,26 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     });
   };
   ZIn zcur;
-  zload(0, zcur);
+  if constexpr (!GROUPED) zload(0, zcur);
   for (int m = 0; m < jb.M; ++m) {
     gf2* __restrict__ Z = Z0 + static_cast<size_t>(m) * N * N;
     const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
-    ZIn znext;
-    if (m + 1 < jb.M) zload(m + 1, znext);
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
     };
-    fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
+    if constexpr (GROUPED) {
+      auto ld_z = [&](int line, int t) {
+        int u = t + N / 2;
+        if (u >= NL) u -= NL;
+        return u < N ? ldv(Z, u * N + line) : make_float2(0.f, 0.f);
+      };
+      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_z, st_chi);
+    } else {
+      ZIn znext;
+      if (m + 1 < jb.M) zload(m + 1, znext);
+      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
+      zcur = znext;
+    }
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * CNT, line = e % G, i = e / G;
@@ -581,10 +607,17 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
       go[q].y = fmaf(sig, pc.y, go[q].y);
       // Re( conj(chi) P Osh ) = Re( conj(conj(P) chi) Osh )
       sgsum += pc.x * o[q].x + pc.y * o[q].y;
-      if (want_probe) stv(Z, i * N + line, cscale(cmulconj(o[q], chi), sig));
+      if (want_probe) {
+        const float2 term = cscale(cmulconj(o[q], chi), sig);
+        if (group_acc) {
+          float2& a = pacc[(m * N + i) * G + line];  // one owner thread per element
+          a = cadd(a, term);
+        } else {
+          stv(Z, i * N + line, term);
+        }
+      }
     }
     __syncthreads();
-    zcur = znext;
   }
   {
     const float s = block_sum<CNT>(sgsum, red);
@@ -616,10 +649,21 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   const float s = block_sum<CNT>(dsum, red);
   if (tid == 0)
     gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s * invN;
+  }  // positions of the group
+  if (group_acc && cbeg < cend) {
+    gf2* __restrict__ Zg = gmem(jb.Y) + (static_cast<size_t>(cbeg) * jb.L + l) * jb.M * N * N + x0;
+    for (int m = 0; m < jb.M; ++m) {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * CNT, line = e % G, i = e / G;
+        stv(Zg + static_cast<size_t>(m) * N * N, i * N + line, pacc[(m * N + i) * G + line]);
+      }
+    }
+  }
 }
 
 // ------------------------------------------- probe gradient: ordered k sum
-// g_probe[l][m][pix] += sum_{c ascending} Y[c][l][m][pix]
+// g_probe[l][m][pix] += sum over groups, ascending, of Y[first c of group][l][m][pix]
 // units: (l, m * nblk + pixel block), nblk = ceil(N^2 / NT)
 __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   const UnitRef r = decode<1>(la);
@@ -636,7 +680,8 @@ __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   gf2* __restrict__ gp = gmem(jb.g_probe);
   float2 acc = ldv(gp, static_cast<size_t>(lm) * plane + pix);
   const int C = min(jb.C, jb.K - la.iter * jb.C);
-  for (int c = 0; c < C; ++c) acc = cadd(acc, ldv(src, c * stride));
+  const int PG = jb.probe_group;  // one summed term per group of positions
+  for (int c = 0; c < C; c += PG) acc = cadd(acc, ldv(src, c * stride));
   stv(gp, static_cast<size_t>(lm) * plane + pix, acc);
 }
 
@@ -909,6 +954,23 @@ int rows_per_adj_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 int rows_per_row_block(int N) { return N == 64 ? 32 : (N <= 256 ? 16 : 8); }
 int col_group_of(int N) { return N <= 256 ? 16 : 8; }
 
+constexpr int kProbeGroup = 4;
+// LDS a column-adjoint block may use (gfx950: 160 KB per workgroup), less a
+// margin for the reduction scratch.
+constexpr size_t kColAdjLds = 156 * 1024;
+
+int probe_group_of(int N, int M, int nl_max) {
+  const size_t G = static_cast<size_t>(col_group_of(N));
+  const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
+  const size_t buf = static_cast<size_t>(nl_max) * (G + 1) * sizeof(float2);
+  return acc + buf <= kColAdjLds ? kProbeGroup : 1;
+}
+
+size_t col_adj_lds_of(int N, int M, int group) {
+  if (group <= 1) return 0;
+  return static_cast<size_t>(M) * N * col_group_of(N) * sizeof(float2);
+}
+
 hipError_t launch_write_table(int* dst, const int* data, int n, hipStream_t s) {
   for (int off = 0; off < n; off += kTableInts) {
     TablePayload p;
@@ -995,13 +1057,25 @@ hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, hipStream_t s) {
+hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
+                          bool grouped, hipStream_t s) {
   if (units <= 0) return hipSuccess;
   return with_N(N, [&](auto nc) {
     constexpr int NN = decltype(nc)::value;
     return host_pad(nl, [&](auto pc) {
       constexpr int NL = decltype(pc)::value;
-      hipLaunchKernelGGL((k_col_adj<NN, NL>), grid1(units * (NN / col_group<NN>())), dim3(CNT), 0, s, la);
+      const dim3 g = grid1(units * (NN / col_group<NN>()));
+      if (!grouped) {
+        hipLaunchKernelGGL((k_col_adj<NN, NL, false>), g, dim3(CNT), 0, s, la);
+        return hipGetLastError();
+      }
+      if (dyn_lds) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&k_col_adj<NN, NL, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn_lds));
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL((k_col_adj<NN, NL, true>), g, dim3(CNT), dyn_lds, s, la);
       return hipGetLastError();
     }, typename PadList<NN>::type{});
   });

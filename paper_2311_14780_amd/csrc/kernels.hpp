@@ -53,6 +53,8 @@ struct JobDev {
   int C;                // positions per chunk (iteration i covers [i C, i C + C))
   int n_loss;           // loss partials per position
   int want_adjoint;
+  int probe_group;      // positions whose probe-gradient terms one column-adjoint
+                        // block sums in LDS (1: one term per position)
   // Flat float views selected by a segment's l in the gradient-zeroing
   // (0 object, 1 probe, 2 positions, 3 sigma) and Adam (0..2) launches.
   // The host fills them so that those kernels pick their arrays by index:
@@ -114,6 +116,12 @@ int rows_per_det_block(int N);
 int rows_per_adj_block(int N);
 int rows_per_row_block(int N);
 int col_group_of(int N);
+// Positions per probe-gradient group for a job (depends only on the job):
+// the column adjoint keeps an M x N x G accumulator in LDS when it fits.
+int probe_group_of(int N, int M, int nl_max);
+// Dynamic LDS bytes of the column adjoint for a job with M modes (0 if the
+// job's group is 1).
+size_t col_adj_lds_of(int N, int M, int group);
 
 // Launchers (asynchronous on `s`).  `units` is the total number of work
 // units of the launch's segments.
@@ -129,7 +137,10 @@ hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& l
 hipError_t launch_resample_loss(int N, const Launch& la, long long units, const LossDev& loss,
                                 bool forward, hipStream_t s);
 hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream_t s);
-hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, hipStream_t s);
+// grouped: some job of the launch sums its probe-gradient terms over groups
+// of positions (else the single-position instance runs)
+hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
+                          bool grouped, hipStream_t s);
 hipError_t launch_row_adj(int N, const Launch& la, long long units, hipStream_t s);
 
 }  // namespace ptycho

@@ -65,7 +65,7 @@ def _ws_bytes(j, which=1, chunk=0):
 
 
 def test_workspace_bytes_scale_with_chunk():
-    j = _job()
+    j = _job(K=20)
     c_all, b_all = _ws_bytes(j)
     c_one, b_one = _ws_bytes(j, chunk=1)
     assert c_all == 0 and c_one == 0
@@ -73,6 +73,12 @@ def test_workspace_bytes_scale_with_chunk():
     # per position: X, GX (L N^2 c64 each), Y (L M N^2 c64), ramps, partials
     per = 8 * 64 * 64 * (2 * 2 + 2 * 3)
     assert b_all - b_one >= 3 * per
+    # loss + gradient calls take positions in groups of 4 for the probe
+    # gradient: a smaller chunk is rounded up to the group
+    assert _ws_bytes(j, chunk=1) == _ws_bytes(j, chunk=4)
+    assert _ws_bytes(j, chunk=5) == _ws_bytes(j, chunk=8)
+    # the forward pass does not group positions
+    assert _ws_bytes(j, which=0, chunk=1)[1] < _ws_bytes(j, which=0, chunk=2)[1]
 
 
 @pytest.mark.parametrize("change,code", [

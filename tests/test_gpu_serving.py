@@ -39,7 +39,7 @@ def test_each_job_is_the_same_alone_and_in_the_mix():
     for r in reqs:
         print("job", r.job_id, "N", r.N, "L", r.L, "M", r.M, "K", r.K, "pads", r.pads, flush=True)
     # a small workspace forces several position chunks per fused call
-    ex = S.TorchExecutor(DEV, 24 << 20, keep_final=True)
+    ex = S.TorchExecutor(DEV, 32 << 20, keep_final=True)
 
     class Ticking(S.Executor):
         def __init__(self, inner, clock):
