@@ -145,6 +145,21 @@ def cpu_baseline(w, truth, start, budget_s: float = 12.0, max_positions: int = 2
                         f"process, {elapsed:.1f} s; host has {os.cpu_count()} logical CPUs"))
 
 
+def copy_calibration(mib: int) -> int:
+    """Three plain device-to-device copies of ``mib`` MiB: each reads and
+    writes exactly ``mib`` MiB, which fixes the scale of the HBM byte
+    counters for the kernels of a step."""
+    import torch
+    a = torch.ones(mib * 2**18, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "copies": 3}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +171,12 @@ def main(argv=None):
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=16)
     ap.add_argument("--serving-iters", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three plain device copies of MIB MiB (the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args(argv)
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU position-sharded design is not built)", file=sys.stderr)
