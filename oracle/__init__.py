@@ -11,7 +11,9 @@ for differentiable scan positions (Section "Benchmarking with state-of-art
 open-source ptychography algorithm").
 
 Pins (tests/test_oracle_*.py) tie it to results fixed independently of its
-own code: brute-force DFT double sums, closed-form shifts of single Fourier
+own code: brute-force DFT double sums (also for the exact-ratio propagator,
+which reduces to the zero-padded DFT at integer ratios and has closed forms
+for discrete plane waves), closed-form shifts of single Fourier
 modes, Parseval, the adjoint identity of every linear operator, zero loss and
 gradient at the noiseless truth, invariance under unitary mode mixing, gauge
 identities of the gradient and central finite differences.
@@ -19,13 +21,13 @@ identities of the gradient and central finite differences.
 
 from .model import (
     split_positions, shift_patch, shift_patch_adjoint, propagate,
-    propagate_adjoint, resample, resample_adjoint, forward, loss_grad,
-    pointwise_loss, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN, LOSS_VJP,
+    propagate_adjoint, is_ratio, scaled_dft_matrix, resample, resample_adjoint,
+    forward, loss_grad, pointwise_loss, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN, LOSS_VJP,
 )
 
 __all__ = [
     "split_positions", "shift_patch", "shift_patch_adjoint", "propagate",
-    "propagate_adjoint", "resample", "resample_adjoint", "forward",
-    "loss_grad", "pointwise_loss", "LOSS_AMPLITUDE", "LOSS_POISSON",
+    "propagate_adjoint", "is_ratio", "scaled_dft_matrix", "resample",
+    "resample_adjoint", "forward", "loss_grad", "pointwise_loss", "LOSS_AMPLITUDE", "LOSS_POISSON",
     "LOSS_GAUSSIAN", "LOSS_VJP",
 ]

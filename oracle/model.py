@@ -21,6 +21,14 @@ design notes):
   N_l x N_l zero array, a unitary 2D DFT is taken and the N x N bins with
   frequencies u in [-N/2, N/2) are kept, DC at index (N/2, N/2).  N_l is an
   input (the per-wavelength detector sampling).
+* f4 with an exact sampling ratio (the chirp z-transform propagator of the
+  section "Benchmarking with state-of-art open-source ptychography
+  algorithm"): when N_l is given as a float alpha (alpha = N lambda_l /
+  lambda_min, generally not an integer), the propagator is the scaled DFT
+  Psi[u, v] = alpha^-1 sum_{r, s} psi[r, s] exp(-2 pi i (u r + v s) / alpha)
+  over the same output bins u, v in [-N/2, N/2).  For an integer alpha this
+  is exactly the zero-padded DFT above; the chirp z-transform is one way to
+  evaluate it, the oracle evaluates the sum as written.
 * sigma_k multiplies the field, as written in Eq. 1.
 * f5: I' = R(I + B) with R an optional bilinear resampling table (tilted
   plane) and B the additive background; the binary mask weights the loss.
@@ -76,9 +84,29 @@ def _crop_index(N: int, nl: int) -> np.ndarray:
     return (np.arange(N) - N // 2) % nl
 
 
-def propagate(psi: np.ndarray, nl: int) -> np.ndarray:
-    """Zero-pad the N x N exit wave to nl x nl, unitary DFT, keep N x N bins."""
+def is_ratio(nl) -> bool:
+    """A float N_l is an exact sampling ratio (scaled DFT); an integer is a
+    zero-padded DFT size."""
+    return isinstance(nl, (float, np.floating))
+
+
+def scaled_dft_matrix(N: int, alpha: float) -> np.ndarray:
+    """F[j, r] = exp(-2 pi i u_j r / alpha) / sqrt(alpha), u_j = j - N/2:
+    one axis of the exact-ratio propagator (rows are output bins)."""
+    u = np.arange(N, dtype=np.float64) - N // 2
+    r = np.arange(N, dtype=np.float64)
+    return np.exp(-2j * np.pi * np.outer(u, r) / alpha) / np.sqrt(alpha)
+
+
+def propagate(psi: np.ndarray, nl) -> np.ndarray:
+    """Zero-pad the N x N exit wave to nl x nl, unitary DFT, keep N x N bins;
+    for a float ``nl`` (exact ratio alpha) the scaled DFT F psi F^T."""
     N = psi.shape[-1]
+    if is_ratio(nl):
+        if not nl >= N:
+            raise ValueError("sampling ratio smaller than the window")
+        F = scaled_dft_matrix(N, float(nl))
+        return F @ psi @ F.T
     if nl < N:
         raise ValueError("pad smaller than the window")
     z = np.zeros((nl, nl), dtype=np.complex128)
@@ -88,9 +116,13 @@ def propagate(psi: np.ndarray, nl: int) -> np.ndarray:
     return F[np.ix_(idx, idx)]
 
 
-def propagate_adjoint(G: np.ndarray, nl: int) -> np.ndarray:
-    """Adjoint of ``propagate``: embed the bins, unitary inverse DFT, crop."""
+def propagate_adjoint(G: np.ndarray, nl) -> np.ndarray:
+    """Adjoint of ``propagate``: embed the bins, unitary inverse DFT, crop;
+    for a float ``nl``, F^H G conj(F)."""
     N = G.shape[-1]
+    if is_ratio(nl):
+        F = scaled_dft_matrix(N, float(nl))
+        return F.conj().T @ G @ F.conj()
     z = np.zeros((nl, nl), dtype=np.complex128)
     idx = _crop_index(N, nl)
     z[np.ix_(idx, idx)] = G

@@ -11,11 +11,11 @@ not available: see ``synth.configs`` for the five workloads.
 """
 
 from .configs import WORKLOADS, Workload, get_workload, reduced
-from .geometry import smooth_pad, pads_for, is_smooth7
+from .geometry import smooth_pad, pads_for, ratios_for, is_smooth7
 from .fields import make_truth, make_start, sample_counts, synthetic_counts
 
 __all__ = [
     "WORKLOADS", "Workload", "get_workload", "reduced",
-    "smooth_pad", "pads_for", "is_smooth7",
+    "smooth_pad", "pads_for", "ratios_for", "is_smooth7",
     "make_truth", "make_start", "sample_counts", "synthetic_counts",
 ]

@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 from scipy.ndimage import gaussian_filter
 
-from .geometry import pads_for, positions_for
+from .geometry import pads_for, positions_for, ratios_for
 
 
 def _rescale(x: np.ndarray, lo: float, hi: float) -> np.ndarray:
@@ -86,7 +86,8 @@ def make_truth(w, Ns: int | None = None) -> dict:
 
     Returns a dict with complex128 ``object`` [L][Ns][H][W], complex128
     ``probe`` [L][M][N][N], float32 ``pos`` [K][2] (y, x top-left of the
-    window in object pixels), ``pads`` (N_l per wavelength), ``sigma`` /
+    window in object pixels), ``pads`` (N_l per wavelength), ``ratios`` (the
+    exact sampling ratio per wavelength, floats), ``sigma`` /
     ``background`` / ``mask`` (None: all ones / zero / all valid).
     """
     rng = np.random.Generator(np.random.PCG64(w.seed))
@@ -96,6 +97,7 @@ def make_truth(w, Ns: int | None = None) -> dict:
     pos = positions_for(w, rng)
     truth = dict(object=obj, probe=prb, pos=pos,
                  pads=pads_for(w.N, w.harmonics, w.ref_harmonic),
+                 ratios=ratios_for(w.N, w.harmonics, w.ref_harmonic),
                  sigma=None, background=None, mask=None, resample=None)
     if w.tilt:
         from .tilt import tilt_table

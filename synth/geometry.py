@@ -7,7 +7,8 @@ wavelength lambda_l is sampled by zero-padding the exit wave to an
 N_l x N_l grid before a unitary DFT, N_l ~ N * lambda_l / lambda_min.  The
 exact ratio is rarely an integer with small prime factors, so N_l is the
 2,3,5,7-smooth integer nearest to it (ties to the larger), and exactly N at the
-reference wavelength.
+reference wavelength.  ``ratios_for`` gives the exact ratios themselves, for
+the exact-ratio (chirp z-transform) propagator.
 """
 from __future__ import annotations
 
@@ -43,6 +44,12 @@ def pads_for(N: int, harmonics, ref_harmonic: int) -> tuple:
     """N_l per wavelength; lambda_l / lambda_ref = ref_harmonic / q_l."""
     return tuple(smooth_pad(N, ref_harmonic / q) if q != ref_harmonic else N
                  for q in harmonics)
+
+
+def ratios_for(N: int, harmonics, ref_harmonic: int) -> tuple:
+    """Exact sampling ratio per wavelength, N * lambda_l / lambda_ref =
+    N * ref_harmonic / q_l, as Python floats (exactly N at the reference)."""
+    return tuple(float(N) * ref_harmonic / q for q in harmonics)
 
 
 def raster_uniform(side: int, step: float, origin: float, jitter: float,

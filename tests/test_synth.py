@@ -5,6 +5,7 @@ import os
 import numpy as np
 import pytest
 
+import synth
 from synth import configs, fields, geometry, tilt
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -126,3 +127,18 @@ def test_sample_counts_deterministic():
     b = fields.sample_counts(I, 3)
     assert a.dtype == np.float32 and np.array_equal(a, b)
     assert np.all(a == np.round(a))
+
+
+def test_exact_ratios_are_wavelength_ratios():
+    # alpha_l = N lambda_l / lambda_ref with lambda proportional to 1/q
+    for name in ("C2", "C3", "C5"):
+        w = synth.get_workload(name)
+        r = synth.ratios_for(w.N, w.harmonics, w.ref_harmonic)
+        pads = synth.pads_for(w.N, w.harmonics, w.ref_harmonic)
+        for q, a, p in zip(w.harmonics, r, pads):
+            assert isinstance(a, float)
+            assert abs(a * q - w.N * w.ref_harmonic) <= 1e-9 * a * q
+            if q == w.ref_harmonic:
+                assert a == float(w.N)
+            # the smooth pad is within the documented 1.65 % of the ratio
+            assert abs(p - a) <= 0.0165 * a
