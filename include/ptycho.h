@@ -29,6 +29,15 @@
  *  - Propagation at wavelength l: the N x N exit wave is zero-padded to
  *    pad[l] x pad[l], a unitary DFT is taken and the N x N bins with signed
  *    frequencies in [-N/2, N/2) are kept (DC at index (N/2, N/2)).
+ *    With ratio[l] = alpha > 0 instead, the propagator is the exact-ratio
+ *    scaled DFT that the paper evaluates with a chirp z-transform (Section
+ *    "Benchmarking with state-of-art open-source ptychography algorithm"):
+ *    per axis Psi[j] = alpha^-1/2 sum_r psi[r] exp(-2 pi i (j - N/2) r / alpha),
+ *    j, r in [0, N).  alpha = N lambda_l / lambda_min samples every
+ *    wavelength on the detector grid without rounding the ratio; an integer
+ *    alpha gives exactly the zero-padded DFT of size alpha.  It is computed
+ *    by Bluestein's method with FFTs of length 2N (about twice the work of a
+ *    zero-padded DFT of similar size).
  *  - Gradients follow G = dL/dRe + i dL/dIm (the convention of autodiff
  *    frameworks' .grad for complex tensors).
  *  - All work is enqueued on `stream` (a hipStream_t, NULL = default) and is
@@ -61,7 +70,7 @@ extern "C" {
 enum {
   PTYCHO_OK = 0,
   PTYCHO_EINVAL = -1,       /* NULL pointer, negative or inconsistent size */
-  PTYCHO_ERANGE = -2,       /* window outside the object, pad < N */
+  PTYCHO_ERANGE = -2,       /* window outside the object, pad < N or ratio < N */
   PTYCHO_EUNSUPPORTED = -3, /* N or pad size not compiled into the library */
   PTYCHO_ENOSPC = -4,       /* workspace smaller than the minimum */
   PTYCHO_EHIP = -5          /* HIP runtime or launch error */
@@ -84,7 +93,12 @@ typedef struct ptycho_job {
   int32_t N;   /* window = detector size, N x N (see ptycho_supported) */
   int32_t H;   /* object height, >= N */
   int32_t W;   /* object width, >= N */
-  int32_t pad[PTYCHO_MAX_WAVELENGTHS]; /* DFT size per wavelength, pad[l] >= N */
+  int32_t pad[PTYCHO_MAX_WAVELENGTHS]; /* DFT size per wavelength, pad[l] >= N (ignored
+                                          where ratio[l] != 0) */
+  double ratio[PTYCHO_MAX_WAVELENGTHS]; /* exact sampling ratio alpha_l >= N of the
+                                           exact-ratio propagator, or 0 (zero-padded DFT
+                                           of size pad[l]); negative, NaN or infinite:
+                                           PTYCHO_EINVAL; 0 < alpha < N: PTYCHO_ERANGE */
   float* object;            /* complex64 [L][H][W]   O_l; written only by ptycho_step */
   float* probe;             /* complex64 [L][M][N][N] P_{l,m}; written only by ptycho_step */
   float* pos;               /* float32 [K][2]        s_k = (y, x); written only by ptycho_step */
@@ -143,7 +157,7 @@ int32_t ptycho_supported(int32_t N, int32_t pad);
    calls process the positions of a job in groups of up to 4 (the probe
    gradient of a group is summed in on-chip memory), so for them `chunk` is
    rounded up to a multiple of the job's group size.  Only the size fields
-   (K, L, M, N, H, W, pad) and whether rs_idx is non-NULL are read: the array
+   (K, L, M, N, H, W, pad, ratio) and whether rs_idx is non-NULL are read: the array
    pointers may be NULL, so a scheduler can size a call before allocating. */
 int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t which,
                                int32_t chunk, size_t* bytes);

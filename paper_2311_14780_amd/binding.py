@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,6 +40,7 @@ _c_p = ctypes.c_void_p
 class JobT(ctypes.Structure):
     _fields_ = [("K", _c_i32), ("L", _c_i32), ("M", _c_i32), ("N", _c_i32), ("H", _c_i32),
                 ("W", _c_i32), ("pad", _c_i32 * MAX_WAVELENGTHS),
+                ("ratio", ctypes.c_double * MAX_WAVELENGTHS),
                 ("object", _c_p), ("probe", _c_p), ("pos", _c_p), ("sigma", _c_p),
                 ("background", _c_p), ("mask", _c_p), ("rs_idx", _c_p), ("rs_w", _c_p),
                 ("rsT_ptr", _c_p), ("rsT_col", _c_p), ("rsT_val", _c_p), ("measured", _c_p)]
@@ -135,7 +137,9 @@ class Problem:
     """Device tensors of one reconstruction job (the variables of Eq. 1).
 
     object complex64 [L][H][W]; probe complex64 [L][M][N][N]; pos float32
-    [K][2]; pads: DFT size per wavelength; measured float32 [K][N][N];
+    [K][2]; pads: per wavelength, an int (zero-padded DFT size) or a float
+    (exact sampling ratio alpha of the exact-ratio propagator); measured
+    float32 [K][N][N];
     sigma float32 [K]; background float32 [N][N]; mask uint8 [N][N];
     resample: (idx int32 [N*N][4], w float32 [N*N][4], ptr, col, val) on
     the device, see ``resample_tables``.
@@ -172,8 +176,7 @@ class Problem:
         j.H, j.W = int(self.object.shape[-2]), int(self.object.shape[-1])
         if len(self.pads) != self.L:
             raise ValueError("one pad per wavelength is required")
-        for l, p in enumerate(self.pads):
-            j.pad[l] = int(p)
+        _set_pads(j, self.pads)
         j.object = _ptr(self.object)
         j.probe = _ptr(self.probe)
         j.pos = _ptr(self.pos)
@@ -186,6 +189,15 @@ class Problem:
             j.rsT_ptr, j.rsT_col, j.rsT_val = _ptr(ptr), _ptr(col), _ptr(val)
         j.measured = _ptr(self.measured)
         return j
+
+
+def _set_pads(j: JobT, pads) -> None:
+    """Integers are zero-padded DFT sizes, floats exact sampling ratios."""
+    for l, p in enumerate(pads):
+        if isinstance(p, (float, np.floating)):
+            j.pad[l], j.ratio[l] = 0, float(p)
+        else:
+            j.pad[l], j.ratio[l] = int(p), 0.0
 
 
 def _jobs(problems: Sequence[Problem]):
@@ -214,8 +226,7 @@ def workspace_bytes_for_shapes(shapes: Sequence[tuple], which: int = 1, chunk: i
     arr = (JobT * len(shapes))()
     for i, (K, L, M, N, H, W, pads) in enumerate(shapes):
         arr[i].K, arr[i].L, arr[i].M, arr[i].N, arr[i].H, arr[i].W = K, L, M, N, H, W
-        for l, p in enumerate(pads):
-            arr[i].pad[l] = int(p)
+        _set_pads(arr[i], pads)
     out = ctypes.c_size_t(0)
     code = lib().ptycho_workspace_bytes(arr, len(shapes), int(which), int(chunk), ctypes.byref(out))
     if code:

@@ -31,8 +31,8 @@ struct DeviceTables {
 std::mutex g_mutex;
 std::map<int, DeviceTables> g_tables;  // device id -> tables
 
-const int kLengths[] = {64,  72,  80,  84,  90,  96,  128, 140, 150, 168, 189, 256, 280,
-                        300, 315, 336, 343, 375, 384, 420, 480, 512, 560, 600, 675, 750};
+const int kLengths[] = {64,  72,  80,  84,  90,  96,  128, 140, 150, 168, 189, 256, 280, 300,
+                        315, 336, 343, 375, 384, 420, 480, 512, 560, 600, 675, 750, 768, 1024};
 
 }  // namespace
 
@@ -186,6 +186,12 @@ int validate_job(const ptycho_job_t& j, bool need_measured, bool check_ptrs = tr
   for (int n : {64, 128, 256, 384, 512}) n_ok |= (j.N == n);
   if (!n_ok) return PTYCHO_EUNSUPPORTED;
   for (int l = 0; l < j.L; ++l) {
+    const double a = j.ratio[l];
+    if (a != 0.0) {  // exact-ratio propagator
+      if (!std::isfinite(a) || a < 0.0) return PTYCHO_EINVAL;
+      if (a < j.N) return PTYCHO_ERANGE;
+      continue;
+    }
     if (j.pad[l] < j.N) return PTYCHO_ERANGE;
     if (!supported(j.N, j.pad[l])) return PTYCHO_EUNSUPPORTED;
   }
@@ -198,6 +204,24 @@ int validate_job(const ptycho_job_t& j, bool need_measured, bool check_ptrs = tr
                   (j.rsT_col != nullptr) + (j.rsT_val != nullptr);
   if (nrs != 0 && nrs != 5) return PTYCHO_EINVAL;
   return PTYCHO_OK;
+}
+
+bool is_czt(const ptycho_job_t& j, int l) { return j.ratio[l] != 0.0; }
+
+bool any_czt(const ptycho_job_t& j) {
+  for (int l = 0; l < j.L; ++l)
+    if (is_czt(j, l)) return true;
+  return false;
+}
+
+// DFT length the kernels run for wavelength l: the pad, or the Bluestein
+// length of the exact-ratio propagator.
+int eff_pad(const ptycho_job_t& j, int l) { return is_czt(j, l) ? czt_len(j.N) : j.pad[l]; }
+
+// Chirp tables of a job's exact-ratio wavelengths (one region per wavelength).
+size_t czt_table_bytes(const ptycho_job_t& j) {
+  return any_czt(j) ? static_cast<size_t>(j.L) * align_up(4 * static_cast<size_t>(j.N) * sizeof(float2))
+                    : 0;
 }
 
 int n_loss_of(const ptycho_job_t& j) {
@@ -230,16 +254,21 @@ size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
   b += align_up(sizeof(JobDev) * n_jobs);                           // job table
   b += align_up(sizeof(Seg) * static_cast<size_t>(kSegsPerJob) * n_jobs);  // segment pool
   for (int i = 0; i < n_jobs; ++i) b += align_up(std::max<size_t>(jobs[i].K, 1) * sizeof(double));
+  for (int i = 0; i < n_jobs; ++i) b += czt_table_bytes(jobs[i]);
   return b;
 }
 
 // Key of a launch group: jobs of one group share every kernel instance.
+// `wide` (some wavelength uses the exact-ratio propagator) selects the
+// detector-kernel instance, so it is part of the key: a job's instances never
+// depend on the other jobs of a call.
 struct GroupKey {
   int N;
   bool resample;
   bool adjoint;
+  bool wide;
   bool operator<(const GroupKey& o) const {
-    return std::tie(N, resample, adjoint) < std::tie(o.N, o.resample, o.adjoint);
+    return std::tie(N, resample, adjoint, wide) < std::tie(o.N, o.resample, o.adjoint, o.wide);
   }
 };
 
@@ -258,6 +287,7 @@ struct Call {
   JobDev* jobs_dev = nullptr;
   Seg* seg_pool = nullptr;
   std::vector<double*> loss_k;
+  std::vector<char*> czt_tab;  // per job, or null
   char* chunk_base = nullptr;
   size_t chunk_bytes = 0;
   std::vector<JobDev> host_jobs;
@@ -267,7 +297,7 @@ struct Call {
 
 int max_pad(const ptycho_job_t& j) {
   int m = j.N;
-  for (int l = 0; l < j.L; ++l) m = std::max(m, j.pad[l]);
+  for (int l = 0; l < j.L; ++l) m = std::max(m, eff_pad(j, l));
   return m;
 }
 
@@ -304,6 +334,12 @@ int layout(Call& c, void* ws, size_t ws_bytes) {
   for (int i = 0; i < c.n; ++i) {
     c.loss_k[i] = reinterpret_cast<double*>(p);
     p += align_up(std::max<size_t>(c.jobs[i].K, 1) * sizeof(double));
+  }
+  c.czt_tab.assign(c.n, nullptr);
+  for (int i = 0; i < c.n; ++i) {
+    const size_t tb = czt_table_bytes(c.jobs[i]);
+    if (tb) c.czt_tab[i] = p;
+    p += tb;
   }
   if (p > end) return PTYCHO_ENOSPC;
   c.chunk_base = p;
@@ -377,10 +413,15 @@ void fill_job(Call& c, int i, char** cursor) {
   d.W = j.W;
   d.tw_N = twiddles(j.N);
   for (int l = 0; l < kMaxL; ++l) {
-    const int nl = l < j.L ? j.pad[l] : j.N;
+    const int nl = l < j.L ? eff_pad(j, l) : j.N;
     d.pad[l] = nl;
     d.pad_scale[l] = static_cast<float>(1.0 / std::sqrt(static_cast<double>(nl)));
     d.tw_pad[l] = twiddles(nl);
+    if (l < j.L && is_czt(j, l)) {
+      d.czt[l] = reinterpret_cast<float2*>(c.czt_tab[i] + l * align_up(4 * static_cast<size_t>(j.N) *
+                                                                        sizeof(float2)));
+      d.czt_alpha[l] = j.ratio[l];
+    }
   }
   if (c.grads) {
     const ptycho_grads_t& g = c.grads[i];
@@ -508,11 +549,16 @@ int run_prologue(Call& c, hipStream_t s) {
   for (int i = 0; i < c.n; ++i) ph.add(stat, i, 0, 1);
   auto val = ph.begin();
   for (int i = 0; i < c.n; ++i) ph.add(val, i, 0, (c.jobs[i].K + 255) / 256);
+  auto czt = ph.begin();
+  for (int i = 0; i < c.n; ++i)
+    for (int l = 0; l < c.jobs[i].L; ++l)
+      if (is_czt(c.jobs[i], l)) ph.add(czt, i, l, czt_table_blocks(c.jobs[i].N));
   int e = upload_phase(c, ph, s);
   if (e) return e;
   LAUNCH(KC_FILL, launch_simple(KZeroGrads, launch_of(c, zero, 0), zero.units, s));
   LAUNCH(KC_PREP, launch_simple(KSetStatus, launch_of(c, stat, 0), stat.units, s));
   LAUNCH(KC_PREP, launch_simple(KValidate, launch_of(c, val, 0), val.units, s));
+  LAUNCH(KC_PREP, launch_simple(KCztTables, launch_of(c, czt, 0), czt.units, s));
   return PTYCHO_OK;
 }
 
@@ -536,15 +582,18 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowf, members[q], l, cnt[q]);
   // distinct DFT sizes of the group, in first-seen order
   std::vector<int> nls;
-  for (int i : members)
+  const bool wide = key.wide;
+  for (int i : members) {
     for (int l = 0; l < c.jobs[i].L; ++l)
-      if (std::find(nls.begin(), nls.end(), c.jobs[i].pad[l]) == nls.end()) nls.push_back(c.jobs[i].pad[l]);
+      if (std::find(nls.begin(), nls.end(), eff_pad(c.jobs[i], l)) == nls.end())
+        nls.push_back(eff_pad(c.jobs[i], l));
+  }
   std::vector<Phase::Item> colf(nls.size()), cola(nls.size());
   for (size_t p = 0; p < nls.size(); ++p) {
     colf[p] = ph.begin();
     for (size_t q = 0; q < members.size(); ++q)
       for (int l = 0; l < c.jobs[members[q]].L; ++l)
-        if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(colf[p], members[q], l, cnt[q]);
+        if (eff_pad(c.jobs[members[q]], l) == nls[p]) ph.add(colf[p], members[q], l, cnt[q]);
   }
   auto det = ph.begin();
   for (size_t q = 0; q < members.size(); ++q) ph.add(det, members[q], 0, cnt[q]);
@@ -555,7 +604,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
       for (size_t q = 0; q < members.size(); ++q) {
         const int pg = c.pgroup[members[q]];
         for (int l = 0; l < c.jobs[members[q]].L; ++l)
-          if (c.jobs[members[q]].pad[l] == nls[p]) ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
+          if (eff_pad(c.jobs[members[q]], l) == nls[p]) ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
       }
     }
     prob = ph.begin();
@@ -590,18 +639,18 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     LAUNCH(KC_COL_FWD, launch_col_fwd(N, nls[p], launch_of(c, colf[p], iter), colf[p].units, s));
   const Launch ldet = launch_of(c, det, iter);
   if (c.which == 0) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, wide, s));
     if (key.resample) LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, true, s));
     return PTYCHO_OK;
   }
   if (!key.resample) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, wide, s));
   } else {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, wide, s));
     LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, false, s));
     if (key.adjoint) {
       LAUNCH(KC_RESAMPLE, launch_resample_T(N, ldet, det.units, s));
-      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, s));
+      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, wide, s));
     }
   }
   if (key.adjoint) {
@@ -611,7 +660,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
       for (size_t q = 0; q < members.size(); ++q) {
         const ptycho_job_t& j = c.jobs[members[q]];
         bool uses = false;
-        for (int l = 0; l < j.L; ++l) uses |= j.pad[l] == nls[p];
+        for (int l = 0; l < j.L; ++l) uses |= eff_pad(j, l) == nls[p];
         if (!uses || !cnt[q]) continue;
         grouped |= c.pgroup[members[q]] > 1;
         lds = std::max(lds, col_adj_lds_of(N, j.M, c.pgroup[members[q]]));
@@ -657,7 +706,8 @@ int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
   // groups of jobs sharing every kernel instance
   std::map<GroupKey, std::vector<int>> groups;
   for (int i = 0; i < c.n; ++i)
-    groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i)}].push_back(i);
+    groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i), any_czt(c.jobs[i])}]
+        .push_back(i);
   c.chunk.assign(c.n, 1);
   c.pgroup.assign(c.n, 1);
   for (int i = 0; i < c.n; ++i)
@@ -711,13 +761,13 @@ int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t
     if (e) return e;
   }
   // chunk region: the largest group needs its jobs' chunks side by side
-  std::map<std::tuple<int, bool>, size_t> group_bytes;
+  std::map<std::tuple<int, bool, bool>, size_t> group_bytes;
   for (int i = 0; i < n_jobs; ++i) {
     const int K = jobs[i].K;
     int c = chunk <= 0 ? std::max(K, 1) : std::max(1, std::min<int>(chunk, std::max(K, 1)));
     // a loss + gradient call may group positions for the probe gradient
     if (which != 0) c = std::max(1, round_chunk(c, K, job_probe_group(jobs[i], true)));
-    group_bytes[std::make_tuple(jobs[i].N, has_resample(jobs[i]))] +=
+    group_bytes[std::make_tuple(jobs[i].N, has_resample(jobs[i]), any_czt(jobs[i]))] +=
         per_position_bytes(jobs[i], which == 0 ? 0 : 1) * static_cast<size_t>(c);
   }
   size_t worst = 0;

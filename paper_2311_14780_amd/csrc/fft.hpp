@@ -299,6 +299,9 @@ PTYCHO_PLAN(560, 16, 5, 7)
 PTYCHO_PLAN(600, 5, 12, 10)
 PTYCHO_PLAN(675, 9, 15, 5)
 PTYCHO_PLAN(750, 5, 15, 10)
+// Bluestein lengths 2N of the exact-ratio propagator (N = 384, 512)
+PTYCHO_PLAN(768, 16, 16, 3)
+PTYCHO_PLAN(1024, 16, 16, 4)
 #undef PTYCHO_PLAN
 
 // Radices of a plan as a host/device array (for building twiddle tables).

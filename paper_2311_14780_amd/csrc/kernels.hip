@@ -56,6 +56,27 @@ template <> struct PadList<256> { using type = IntList<256, 280, 300, 315, 336, 
 template <> struct PadList<384> { using type = IntList<384, 420, 480>; static constexpr int max = 480; };
 template <> struct PadList<512> { using type = IntList<512, 560, 600, 675, 750>; static constexpr int max = 750; };
 
+// Exact-ratio propagator (chirp z-transform, Bluestein's method): per axis
+// Psi[j] = alpha^-1/2 sum_r psi[r] exp(-2 pi i u_j r / alpha), u_j = j - N/2,
+// written as cout[j] sum_r (cin[r] psi[r]) h[j - r] with the chirps
+// cin[r] = exp(-i pi r^2 / alpha), cout[j] = alpha^-1/2 exp(-i pi u_j^2 / alpha)
+// and h[t] = exp(+i pi (t - N/2)^2 / alpha).  The lags j - r span 2N - 1
+// values, so a circular convolution of length 2N evaluates it exactly:
+// FFT, times the kernel's DFT (precomputed per call), inverse FFT.  The
+// length 2N is never a zero-padded DFT size of the same N, so it marks the
+// exact-ratio instances of the DFT-size-templated kernels.
+template <int N> constexpr int czt_nb() { return 2 * N; }
+template <class List, int X> struct Append;
+template <int... Ps, int X> struct Append<IntList<Ps...>, X> { using type = IntList<Ps..., X>; };
+// DFT lengths of the column kernels: the pads, then the Bluestein length.
+template <int N> using ColList = typename Append<typename PadList<N>::type, czt_nb<N>()>::type;
+// Row lengths of a detector-kernel instance.
+template <int N, bool WIDE>
+using DetList = std::conditional_t<WIDE, ColList<N>, typename PadList<N>::type>;
+static_assert(czt_nb<64>() > PadList<64>::max && czt_nb<128>() > PadList<128>::max &&
+              czt_nb<256>() > PadList<256>::max && czt_nb<384>() > PadList<384>::max &&
+              czt_nb<512>() > PadList<512>::max, "the Bluestein length must not be a pad size");
+
 template <int N> constexpr int rb_row() { return N == 64 ? 32 : (N <= 256 ? 16 : 8); }
 template <int N> constexpr int rb_det() { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 template <int N> constexpr int rb_adj() { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
@@ -202,6 +223,63 @@ __global__ __launch_bounds__(NT) void k_prep(Launch la) {
   }
 }
 
+// ------------------------------------------ exact-ratio propagator tables
+// Per (job, wavelength l with alpha_l > 0) the table of czt_nb: cin[N],
+// cout[N] and hk[2N] = DFT_2N(h) / 2N, h[t] = exp(+i pi (t' - N/2)^2 / alpha)
+// at lag t' = t (t < N) or t - 2N (t > N), h[N] = 0 (that lag never occurs).
+// Evaluated in float64 with the chirp arguments reduced exactly
+// (r^2 mod 2 alpha) and rounded to float32 once; the DFT is a plain ordered
+// sum, so the table is the same in every call.
+// units: (job, l) x czt_table_blocks(N): chirp blocks, then kernel blocks
+constexpr int kCztMaxNB = 1024;
+__global__ __launch_bounds__(NT) void k_czt_tables(Launch la) {
+  __shared__ double2 hk[kCztMaxNB];
+  __shared__ double2 tw[kCztMaxNB];
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  const int l = r.l, N = jb.N, NB = 2 * N;
+  const double a = jb.czt_alpha[l];
+  gf2* __restrict__ tb = gmem(jb.czt[l]);
+  const int CB = (2 * N + NT - 1) / NT;  // chirp blocks
+  if (r.u < CB) {
+    const int e = r.u * NT + threadIdx.x;
+    double sn, cs;
+    if (e < N) {
+      sincospi(-fmod(static_cast<double>(e) * e, 2.0 * a) / a, &sn, &cs);
+      stv(tb, e, make_float2(static_cast<float>(cs), static_cast<float>(sn)));
+    } else if (e < 2 * N) {
+      const double u = static_cast<double>(e - N - N / 2);
+      sincospi(-fmod(u * u, 2.0 * a) / a, &sn, &cs);
+      const double sc = 1.0 / sqrt(a);
+      stv(tb, e, make_float2(static_cast<float>(cs * sc), static_cast<float>(sn * sc)));
+    }
+    return;  // block-uniform
+  }
+  for (int t = threadIdx.x; t < NB; t += NT) {
+    double sn = 0.0, cs = 0.0;
+    if (t != N) {
+      const double d = static_cast<double>((t < N ? t : t - NB) - N / 2);
+      sincospi(fmod(d * d, 2.0 * a) / a, &sn, &cs);
+    }
+    hk[t] = make_double2(cs, sn);
+    sincospi(-2.0 * static_cast<double>(t) / NB, &sn, &cs);
+    tw[t] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  const int f = (r.u - CB) * NT + threadIdx.x;
+  if (f >= NB) return;
+  double re = 0.0, im = 0.0;
+  int q = 0;  // f t mod NB
+  for (int t = 0; t < NB; ++t) {
+    const double2 h = hk[t], w = tw[q];
+    re += h.x * w.x - h.y * w.y;
+    im += h.x * w.y + h.y * w.x;
+    q += f;
+    if (q >= NB) q -= NB;
+  }
+  stv(tb, 2 * N + f, make_float2(static_cast<float>(re / NB), static_cast<float>(im / NB)));
+}
+
 // ------------------------------------------------------------- row forward
 // X[c][l][y][:] = IFFT_x( ramp_x * FFT_x( O_l[p_y + y][p_x : p_x + N] ) ) / N
 // units: (l, c) positions of every wavelength
@@ -280,15 +358,30 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
     __syncthreads();
     gf2* __restrict__ Y =
         gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
-    auto ld_psi = [&](int line, int t) {
-      return t < N ? buf[t * LP + line] : make_float2(0.f, 0.f);
-    };
-    auto st_y = [&](int line, int t, float2 v) {
-      int u = t + N / 2;
-      if (u >= NL) u -= NL;
-      if (u < N) stv(Y, u * N + line, cscale(v, ps));
-    };
-    fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_psi, st_y);
+    if constexpr (NL == czt_nb<N>()) {
+      // exact ratio: cin psi -> FFT -> times the kernel DFT -> IFFT -> cout
+      const gf2* __restrict__ tb = gmem(jb.czt[l]);
+      auto ld_c = [&](int line, int t) {
+        return t < N ? cmul(buf[t * LP + line], ldv(tb, t)) : make_float2(0.f, 0.f);
+      };
+      auto st_h = [&](int line, int t, float2 v) { buf[t * LP + line] = cmul(v, ldv(tb, 2 * N + t)); };
+      fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_c, st_h);
+      auto ld_b = [&](int line, int t) { return buf[t * LP + line]; };
+      auto st_y = [&](int line, int t, float2 v) {
+        if (t < N) stv(Y, t * N + line, cmul(v, ldv(tb, N + t)));
+      };
+      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_y);
+    } else {
+      auto ld_psi = [&](int line, int t) {
+        return t < N ? buf[t * LP + line] : make_float2(0.f, 0.f);
+      };
+      auto st_y = [&](int line, int t, float2 v) {
+        int u = t + N / 2;
+        if (u >= NL) u -= NL;
+        if (u < N) stv(Y, u * N + line, cscale(v, ps));
+      };
+      fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_psi, st_y);
+    }
   }
 }
 
@@ -331,17 +424,64 @@ __device__ __noinline__ void det_rows_adj(lf2* buf, const lf32* acc, gf2* __rest
   fft_lines<NL, true, RB, NT, LP, false>(buf, twL, ld, st);
 }
 
+// Exact-ratio row pass: Psi[u][:] = cout (IFFT( FFT(cin Y[u][:]) hk ))[0:N],
+// acc += |Psi|^2 (tb: the wavelength's chirp table, see czt_nb).
+template <int N, int NB, int RB>
+__device__ __noinline__ void det_rows_fwd_czt(lf2* buf, lf32* acc, gf2* __restrict__ Yr,
+                                              const gf2* __restrict__ twB,
+                                              const gf2* __restrict__ tb, bool keep) {
+  constexpr int LP = row_lp(NB);
+  using Ix = Lds<NB, LP, false>;
+  auto ld = [&](int line, int t) {
+    return t < N ? cmul(ldv(Yr, line * N + t), ldv(tb, t)) : make_float2(0.f, 0.f);
+  };
+  auto st = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmul(v, ldv(tb, 2 * N + t))); };
+  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld, st);
+  auto ld2 = [&](int line, int t) { return ldv(buf, Ix::at(line, t)); };
+  auto st2 = [&](int line, int t, float2 v) {
+    if (t < N) {
+      v = cmul(v, ldv(tb, N + t));
+      if (keep) stv(Yr, line * N + t, v);
+      acc[line * N + t] += cabs2(v);
+    }
+  };
+  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld2, st2);
+}
+
+// Its adjoint: Z[u][:] = conj(cin) (IFFT( FFT(conj(cout) g2 Psi[u][:]) conj(hk) ))[0:N],
+// written over Psi.
+template <int N, int NB, int RB>
+__device__ __noinline__ void det_rows_adj_czt(lf2* buf, const lf32* acc, gf2* __restrict__ Yr,
+                                              const gf2* __restrict__ twB,
+                                              const gf2* __restrict__ tb) {
+  constexpr int LP = row_lp(NB);
+  using Ix = Lds<NB, LP, false>;
+  auto ld = [&](int line, int t) {
+    return t < N ? cmulconj(ldv(tb, N + t), cscale(ldv(Yr, line * N + t), acc[line * N + t]))
+                 : make_float2(0.f, 0.f);
+  };
+  auto st = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmulconj(ldv(tb, 2 * N + t), v)); };
+  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld, st);
+  auto ld2 = [&](int line, int t) { return ldv(buf, Ix::at(line, t)); };
+  auto st2 = [&](int line, int t, float2 v) {
+    if (t < N) stv(Yr, line * N + t, cmulconj(ldv(tb, t), v));
+  };
+  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld2, st2);
+}
+
 // MODE 0: fused forward + loss + adjoint; 1: forward, write I + B to out;
 // 2: adjoint from g rows in the resampling buffer; 3: forward + loss only.
 // `spill` (MODE 1) writes Psi back over Y for a later MODE 2.
+// WIDE: the instance for launches with exact-ratio wavelengths (rows of 2N).
 // units: positions c
-template <int N, int MODE>
+template <int N, int MODE, bool WIDE>
 __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill) {
   constexpr int RB = rb_det<N>();
+  using Rows = DetList<N, WIDE>;
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
-  constexpr int LPMAX = max_row_lp(typename PadList<N>::type{});
+  constexpr int LPMAX = max_row_lp(Rows{});
   __shared__ float2 buf[RB * LPMAX];
   __shared__ float acc[RB * N];
   __shared__ float red[NT / 64];
@@ -362,8 +502,11 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
                   static_cast<size_t>(u0) * N;
         pad_switch(nl, [&](auto nlc) {
           constexpr int NL = decltype(nlc)::value;
-          det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), ps, keep);
-        }, typename PadList<N>::type{});
+          if constexpr (NL == czt_nb<N>())
+            det_rows_fwd_czt<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]), keep);
+          else
+            det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), ps, keep);
+        }, Rows{});
       }
     }
     // acc = sum_{l,m} |Psi|^2 for RB rows
@@ -420,8 +563,11 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
                 static_cast<size_t>(u0) * N;
       pad_switch(nl, [&](auto nlc) {
         constexpr int NL = decltype(nlc)::value;
-        det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
-      }, typename PadList<N>::type{});
+        if constexpr (NL == czt_nb<N>())
+          det_rows_adj_czt<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]));
+        else
+          det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
+      }, Rows{});
     }
   }
 }
@@ -567,14 +713,23 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
   gf2* __restrict__ Z0 = gmem(jb.Y) + (static_cast<size_t>(c) * jb.L + l) * jb.M * N * N + x0;
-  using ZIn = PreIn<NL, G, CNT, true>;
-  auto zload = [&](int m, ZIn& zin) {
-    const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
-    fft_first_load(zin, [&](int line, int t) {
+  constexpr bool CZT = NL == czt_nb<N>();
+  const gf2* __restrict__ tb = CZT ? gmem(jb.czt[l]) : nullptr;
+  // first-transform input of mode m at FFT index t: the cropped bins embedded
+  // at their frequencies, or (exact ratio) conj(cout) Z in detector order
+  auto zin_at = [&](const gf2* __restrict__ Zm, int line, int t) {
+    if constexpr (CZT) {
+      return t < N ? cmulconj(ldv(tb, N + t), ldv(Zm, t * N + line)) : make_float2(0.f, 0.f);
+    } else {
       int u = t + N / 2;
       if (u >= NL) u -= NL;
       return u < N ? ldv(Zm, u * N + line) : make_float2(0.f, 0.f);
-    });
+    }
+  };
+  using ZIn = PreIn<NL, G, CNT, true>;
+  auto zload = [&](int m, ZIn& zin) {
+    const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
+    fft_first_load(zin, [&](int line, int t) { return zin_at(Zm, line, t); });
   };
   ZIn zcur;
   if constexpr (!GROUPED) zload(0, zcur);
@@ -584,17 +739,29 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
     };
+    // exact ratio: FFT, times conj(kernel DFT), IFFT, conj(cin)
+    auto st_hc = [&](int line, int t, float2 v) { buf[t * LP + line] = cmulconj(ldv(tb, 2 * N + t), v); };
+    auto ld_b = [&](int line, int t) { return buf[t * LP + line]; };
+    auto st_chic = [&](int line, int t, float2 v) {
+      if (t < N) buf[t * LP + line] = cmulconj(ldv(tb, t), v);
+    };
     if constexpr (GROUPED) {
-      auto ld_z = [&](int line, int t) {
-        int u = t + N / 2;
-        if (u >= NL) u -= NL;
-        return u < N ? ldv(Z, u * N + line) : make_float2(0.f, 0.f);
-      };
-      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_z, st_chi);
+      auto ld_z = [&](int line, int t) { return zin_at(Z, line, t); };
+      if constexpr (CZT) {
+        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_z, st_hc);
+        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
+      } else {
+        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_z, st_chi);
+      }
     } else {
       ZIn znext;
       if (m + 1 < jb.M) zload(m + 1, znext);
-      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
+      if constexpr (CZT) {
+        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, zcur, st_hc);
+        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
+      } else {
+        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
+      }
       zcur = znext;
     }
 #pragma unroll
@@ -934,7 +1101,7 @@ inline dim3 grid1(long long blocks) { return dim3(static_cast<unsigned>(blocks))
 
 int plan_radices(int n, int* out) {
   using All = IntList<64, 72, 80, 84, 90, 96, 128, 140, 150, 168, 189, 256, 280, 300, 315, 336,
-                      343, 375, 384, 420, 480, 512, 560, 600, 675, 750>;
+                      343, 375, 384, 420, 480, 512, 560, 600, 675, 750, 768, 1024>;
   return plan_of(n, out, All{});
 }
 
@@ -948,6 +1115,9 @@ bool supported(int N, int nl) {
     default: return false;
   }
 }
+
+int czt_len(int N) { return 2 * N; }
+int czt_table_blocks(int N) { return (2 * N + NT - 1) / NT + (2 * N + NT - 1) / NT; }
 
 int rows_per_det_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 int rows_per_adj_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
@@ -994,6 +1164,7 @@ hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_
     case KObjGather: hipLaunchKernelGGL(k_obj_gather, grid1(units), dim3(NT), 0, s, la); break;
     case KFinalize: hipLaunchKernelGGL(k_finalize_chunk, grid1(units), dim3(64), 0, s, la); break;
     case KAdam: hipLaunchKernelGGL(k_adam, grid1(units), dim3(NT), 0, s, la); break;
+    case KCztTables: hipLaunchKernelGGL(k_czt_tables, grid1(units), dim3(NT), 0, s, la); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1022,22 +1193,29 @@ hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipS
       constexpr int NL = decltype(pc)::value;
       hipLaunchKernelGGL((k_col_fwd<NN, NL>), grid1(units * (NN / col_group<NN>())), dim3(CNT), 0, s, la);
       return hipGetLastError();
-    }, typename PadList<NN>::type{});
+    }, ColList<NN>{});
   });
 }
 
+template <int NN, bool WIDE>
+void launch_det_inst(dim3 g, const Launch& la, const LossDev& loss, int mode, bool spill,
+                     hipStream_t s) {
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k_det<NN, 0, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
+    case 1: hipLaunchKernelGGL((k_det<NN, 1, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
+    case 2: hipLaunchKernelGGL((k_det<NN, 2, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
+    default: hipLaunchKernelGGL((k_det<NN, 3, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
+  }
+}
+
 hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
-                      bool spill, hipStream_t s) {
+                      bool spill, bool wide, hipStream_t s) {
   if (units <= 0) return hipSuccess;
   return with_N(N, [&](auto nc) {
     constexpr int NN = decltype(nc)::value;
     const dim3 g = grid1(units * (NN / rb_det<NN>()));
-    switch (mode) {
-      case 0: hipLaunchKernelGGL((k_det<NN, 0>), g, dim3(NT), 0, s, la, loss, spill); break;
-      case 1: hipLaunchKernelGGL((k_det<NN, 1>), g, dim3(NT), 0, s, la, loss, spill); break;
-      case 2: hipLaunchKernelGGL((k_det<NN, 2>), g, dim3(NT), 0, s, la, loss, spill); break;
-      default: hipLaunchKernelGGL((k_det<NN, 3>), g, dim3(NT), 0, s, la, loss, spill); break;
-    }
+    if (wide) launch_det_inst<NN, true>(g, la, loss, mode, spill, s);
+    else launch_det_inst<NN, false>(g, la, loss, mode, spill, s);
     return hipGetLastError();
   });
 }
@@ -1077,7 +1255,7 @@ hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size
       }
       hipLaunchKernelGGL((k_col_adj<NN, NL, true>), g, dim3(CNT), dyn_lds, s, la);
       return hipGetLastError();
-    }, typename PadList<NN>::type{});
+    }, ColList<NN>{});
   });
 }
 

@@ -26,10 +26,15 @@ struct JobDev {
   const float* rsT_val;
   const float* measured;  // [K][N][N]
   int K, L, M, N, H, W;
-  int pad[kMaxL];
-  float pad_scale[kMaxL];  // 1 / sqrt(pad[l])
+  int pad[kMaxL];          // DFT length per wavelength (2N for the exact-ratio propagator)
+  float pad_scale[kMaxL];  // 1 / sqrt(pad[l]) (zero-padded DFT only)
   const float2* tw_N;            // twiddles of length N
   const float2* tw_pad[kMaxL];   // twiddles of length pad[l]
+  // Exact-ratio (chirp z-transform) propagator of wavelength l, or null:
+  // [N] exp(-i pi r^2 / alpha) | [N] alpha^-1/2 exp(-i pi u_j^2 / alpha) |
+  // [2N] DFT of the chirp kernel / 2N (workspace, filled by k_czt_tables)
+  float2* czt[kMaxL];
+  double czt_alpha[kMaxL];  // alpha_l (0: zero-padded DFT)
   // outputs (caller memory, each may be null)
   float* loss;
   float2* g_object;
@@ -101,7 +106,11 @@ struct TablePayload {
 };
 
 // Kinds of the simple launches (launch_simple).
-enum SimpleKind { KZeroGrads, KSetStatus, KValidate, KPrep, KProbeReduce, KObjGather, KFinalize, KAdam };
+enum SimpleKind {
+  KZeroGrads, KSetStatus, KValidate, KPrep, KProbeReduce, KObjGather, KFinalize, KAdam, KCztTables
+};
+// Blocks of k_czt_tables per (job, wavelength) with the exact-ratio propagator.
+int czt_table_blocks(int N);
 
 // Radix plan of an FFT length (returns the number of passes, 0 if unknown).
 int plan_radices(int n, int* out);
@@ -112,6 +121,8 @@ int init_twiddles();  // returns 0 or a PTYCHO_E* code
 void release_twiddles();
 
 bool supported(int N, int nl);
+// Bluestein FFT length of the exact-ratio propagator for window N (2N).
+int czt_len(int N);
 int rows_per_det_block(int N);
 int rows_per_adj_block(int N);
 int rows_per_row_block(int N);
@@ -131,9 +142,11 @@ hipError_t launch_loss_total(const Launch& la, long long units, float scale, hip
 hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t s);
 hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s);
 // mode: 0 fused loss + adjoint, 1 forward (I + B to ibuf or out; `spill`
-// keeps Psi for mode 2), 2 adjoint from ibuf (R^T g), 3 loss only
+// keeps Psi for mode 2), 2 adjoint from ibuf (R^T g), 3 loss only.
+// wide: some job of the launch uses the exact-ratio propagator (the
+// instance whose LDS holds rows of length 2N)
 hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
-                      bool spill, hipStream_t s);
+                      bool spill, bool wide, hipStream_t s);
 hipError_t launch_resample_loss(int N, const Launch& la, long long units, const LossDev& loss,
                                 bool forward, hipStream_t s);
 hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream_t s);

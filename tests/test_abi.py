@@ -162,3 +162,44 @@ def test_serving_mix_pads_are_compiled_in():
     for w in SS.serving_jobs(64, 4):
         for p in synth.pads_for(w.N, w.harmonics, w.ref_harmonic):
             assert B.ptycho_supported(w.N, p), (w.N, p)
+
+
+def _job_ratio(ratios, **kw):
+    j = _job(**kw)
+    for l, a in enumerate(ratios):
+        if a:
+            j.pad[l], j.ratio[l] = 0, a
+    return j
+
+
+def test_job_struct_layout():
+    # six int32 sizes, pad[8], then ratio[8] (8-byte aligned), then pointers
+    assert B.JobT.ratio.offset == 56
+    assert B.JobT.object.offset == 56 + 64
+
+
+@pytest.mark.parametrize("ratio,code", [
+    (-1.0, B.PTYCHO_EINVAL), (float("nan"), B.PTYCHO_EINVAL), (float("inf"), B.PTYCHO_EINVAL),
+    (63.5, B.PTYCHO_ERANGE)])
+def test_invalid_ratio_rejected_on_host(ratio, code):
+    j = _job_ratio((0.0, ratio))
+    assert _ws_bytes(j)[0] == code
+    loss = B.LossT(0, 1e-6, 1.0)
+    grads = B.GradsT()
+    rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                                  ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == code
+
+
+def test_ratio_ignores_pad_and_workspace_holds_the_chirp_tables():
+    # the pad of an exact-ratio wavelength is not validated (0 here)
+    j = _job_ratio((0.0, 77.3), K=8)
+    c, b = _ws_bytes(j, chunk=4)
+    assert c == 0
+    ref = _ws_bytes(_job(K=8), chunk=4)[1]
+    # one table of 4N complex64 per wavelength of the job
+    assert b - ref >= 2 * 4 * 64 * 8
+    got = B.workspace_bytes_for_shapes([(8, 2, 3, 64, 128, 128, (64, 77.3))], which=1, chunk=4)
+    assert got == b
+    # an integer-valued ratio is still the exact-ratio propagator
+    assert _ws_bytes(_job_ratio((64.0, 0.0), K=8), chunk=4)[1] > ref
