@@ -93,11 +93,14 @@ def measured_traffic(workload: str, kernel: str):
     return float(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
 
 
-def build_inputs(w, device):
+def build_inputs(w, device, exact_ratio: bool = False):
     import torch
     import synth
     from paper_2311_14780_amd import binding as B
     truth = synth.make_truth(w)
+    if exact_ratio:
+        # the exact wavelength ratios (floats) select the exact-ratio propagator
+        truth["pads"] = truth["ratios"]
     start = synth.make_start(truth, w)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
     res = None
@@ -171,6 +174,9 @@ def main(argv=None):
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=16)
     ap.add_argument("--serving-iters", type=int, default=5)
+    ap.add_argument("--propagator", choices=("pad", "czt"), default="pad",
+                    help="pad: zero-padded DFT at the smooth pad sizes; czt: exact-ratio "
+                         "propagator (scaled DFT by Bluestein's method)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -188,7 +194,8 @@ def main(argv=None):
 
     w = synth.get_workload(args.workload)
     dev = torch.device("cuda:0")
-    truth, start, prob = build_inputs(w, dev)
+    czt = args.propagator == "czt"
+    truth, start, prob = build_inputs(w, dev, exact_ratio=czt)
     K, L, M, N, H, W = w.K, w.L, w.M, w.N, w.H, w.W
     g = dict(loss=torch.zeros(1, device=dev), g_object=torch.zeros_like(prob.object),
              g_probe=torch.zeros_like(prob.probe), g_pos=torch.zeros(K, 2, device=dev),
@@ -240,7 +247,7 @@ def main(argv=None):
         d = kern_out[dom]
         per_launch = alg_bytes(dom, K, L, M, N, H, W) / d["launches_per_step"]
         achieved = per_launch / (d["avg_launch_us"] * 1e-6) / 1e9
-        traffic = measured_traffic(w.name, dom)
+        traffic = None if czt else measured_traffic(w.name, dom)
         roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic / 1e9, 4),
@@ -254,7 +261,9 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, truth, start)
     serving = None
-    pads = list(prob.pads)
+    pads = [round(p, 4) if isinstance(p, float) else int(p) for p in prob.pads]
+    prop = ("exact-ratio propagator (scaled DFT by Bluestein's method, FFT length 2N), ratios "
+            if czt else "zero-padded DFT, pads ")
     if not args.no_serving:
         from paper_2311_14780_amd import serving as S
         del g, adam, ws, prob
@@ -268,9 +277,10 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"{w.name}: {L} wavelengths (harmonics {'/'.join(map(str, w.harmonics))}) "
                                 f"x {M} probe modes, probe {N}x{N}, object {H}x{W} per wavelength, "
-                                f"{K} positions ({w.scan}), pads {'/'.join(map(str, pads))}, "
+                                f"{K} positions ({w.scan}), {prop}{'/'.join(map(str, pads))}, "
                                 f"{w.photons:.0e} photons/pattern; step = loss + gradients + Adam"),
                    "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": pads,
+                   "propagator": "exact-ratio" if czt else "zero-padded DFT",
                    "parallelism": "single GPU"},
         "step_roofline": {"alg_bytes_per_step": b_step,
                           "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),

@@ -229,7 +229,9 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     ``positions`` restricts the sums over k to a subset (the loss is a sum of
     per-position terms, so the full gradient is the sum over a partition).
     Returns a dict: loss (float), g_object (shape of ``obj``), g_probe
-    [L][M][N][N], g_pos [K][2], g_sigma [K] (zero outside the subset).
+    [L][M][N][N], g_pos [K][2], g_sigma [K] (zero outside the subset),
+    g_background [N][N] (the background enters f5 before the resampling, so
+    its gradient is the sum over positions of the pulled-back dL/dI').
     """
     obj, squeeze = _as_object(obj)
     probe = np.asarray(probe, dtype=np.complex128)
@@ -243,6 +245,7 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     g_prb = np.zeros_like(probe)
     g_pos = np.zeros((K, 2))
     g_sig = np.zeros(K)
+    g_bg = np.zeros((N, N))
     total = 0.0
     ks = range(K) if positions is None else positions
     for k in ks:
@@ -260,6 +263,7 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
         g = w * dell
         if resample_table is not None:
             g = resample_adjoint(g, *resample_table)
+        g_bg += g
         ramp = _ramp(N, d[k])
         for l in range(L):
             for n in range(Ns):
@@ -282,5 +286,6 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     g_prb *= scale
     g_pos *= scale
     g_sig *= scale
+    g_bg *= scale
     return dict(loss=total * scale, g_object=g_obj[:, 0] if squeeze else g_obj,
-                g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig)
+                g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig, g_background=g_bg)

@@ -1,6 +1,8 @@
 """Parity at the full sizes of the large multiplexed workload (5 wavelengths
-x 8 modes, 512^2 probe, 3072^2 object, 2500 positions) and the reflection
-workload (3 wavelengths x 4 modes, 384^2 probe, 900 positions, tilt table).
+x 8 modes, 512^2 probe, 3072^2 object, 2500 positions), the reflection
+workload (3 wavelengths x 4 modes, 384^2 probe, 900 positions, tilt table)
+and the benchmark workload (4 wavelengths x 3 modes, 256^2 probe, 400
+positions) with the exact-ratio propagator.
 
 The whole scan runs on the device; the FP64 oracle, which cannot evaluate
 2500 positions in a test, checks what it can compute position by position:
@@ -25,9 +27,11 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _case(name, sigma_seed):
+def _case(name, sigma_seed, exact_ratio=False):
     w = synth.get_workload(name)
     truth = synth.make_truth(w)
+    if exact_ratio:
+        truth["pads"] = truth["ratios"]
     start = synth.make_start(truth, w)
     rng = np.random.default_rng(sigma_seed)
     sigma = rng.uniform(0.8, 1.2, w.K).astype(np.float32)
@@ -108,4 +112,12 @@ def test_reflection_workload_full_size():
     case = _case("C5", 51)
     ks = [0, 451, 899]
     I_gpu, got = _run(case, ks, ws_gb=8)
+    _check(case, ks, I_gpu, got)
+
+
+def test_benchmark_workload_exact_ratios_full_size():
+    case = _case("C2", 21, exact_ratio=True)
+    assert all(isinstance(a, float) for a in case["pads"])
+    ks = [0, 199, 399]
+    I_gpu, got = _run(case, ks, ws_gb=2)
     _check(case, ks, I_gpu, got)

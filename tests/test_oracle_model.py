@@ -107,7 +107,7 @@ def test_zero_gradient_at_noiseless_truth(kind):
                      sigma=pr["sigma"], background=pr["bg"])
     if kind != om.LOSS_POISSON:
         assert abs(r["loss"]) <= 1e-12 * np.sum(meas)
-    for key in ("g_object", "g_probe", "g_pos", "g_sigma"):
+    for key in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
         assert np.max(np.abs(r[key])) < 1e-9, key
 
 
@@ -180,6 +180,13 @@ def test_gradients_match_central_differences(kind, extras):
         fd, an = _fd_check(L_sig, base["g_sigma"], pr["sigma"], v, h)
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), ("sigma", fd, an)
 
+        def L_bg(b):
+            return om.loss_grad(pr["obj"], pr["prb"], pr["pos"], pr["pads"], meas,
+                                **{**kw, "background": b})["loss"]
+        v = rng.normal(size=pr["bg"].shape)
+        fd, an = _fd_check(L_bg, base["g_background"], pr["bg"], v, h)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), ("background", fd, an)
+
 
 def test_position_gradient_matches_fd_in_float64_delta():
     # Tighter check of the Fourier phase-ramp derivative: differentiate the
@@ -247,5 +254,5 @@ def test_loss_is_sum_over_position_subsets():
     a = om.loss_grad(pr["obj"], pr["prb"], pr["pos"], pr["pads"], meas, positions=[0, 2, 4])
     b = om.loss_grad(pr["obj"], pr["prb"], pr["pos"], pr["pads"], meas, positions=[1, 3, 5])
     assert abs(a["loss"] + b["loss"] - full["loss"]) <= 1e-12 * abs(full["loss"])
-    for key in ("g_object", "g_probe", "g_pos"):
+    for key in ("g_object", "g_probe", "g_pos", "g_background"):
         assert np.allclose(a[key] + b[key], full[key], rtol=0, atol=1e-12 * np.max(np.abs(full[key])))
