@@ -102,8 +102,10 @@ typedef struct ptycho_job {
   float* object;            /* complex64 [L][H][W]   O_l; written only by ptycho_step */
   float* probe;             /* complex64 [L][M][N][N] P_{l,m}; written only by ptycho_step */
   float* pos;               /* float32 [K][2]        s_k = (y, x); written only by ptycho_step */
-  const float* sigma;       /* float32 [K] power coefficients sigma_k, or NULL (= 1) */
-  const float* background;  /* float32 [N][N] additive background N(rho), or NULL (= 0) */
+  float* sigma;             /* float32 [K] power coefficients sigma_k, or NULL (= 1);
+                               written only by ptycho_step (lr_sigma != 0) */
+  float* background;        /* float32 [N][N] additive background N(rho), or NULL (= 0);
+                               written only by ptycho_step (lr_background != 0) */
   const uint8_t* mask;      /* uint8 [N][N] loss weight 0/1, or NULL (= all 1) */
   /* Optional bilinear resampling of the predicted pattern (tilted plane):
      I'(a) = sum_{t<4} rs_w[a][t] * I(rs_idx[a][t]), flat indices into N x N.
@@ -128,23 +130,31 @@ typedef struct ptycho_loss {
 /* Outputs, one per job.  Every pointer may be NULL to skip that output
    (a NULL gradient also skips the work that only it needs). */
 typedef struct ptycho_grads {
-  float* loss;      /* float32 [1] */
-  float* g_object;  /* complex64 [L][H][W] */
-  float* g_probe;   /* complex64 [L][M][N][N] */
-  float* g_pos;     /* float32 [K][2] */
-  float* g_sigma;   /* float32 [K] */
+  float* loss;          /* float32 [1] */
+  float* g_object;      /* complex64 [L][H][W] */
+  float* g_probe;       /* complex64 [L][M][N][N] */
+  float* g_pos;         /* float32 [K][2] */
+  float* g_sigma;       /* float32 [K] */
+  float* g_background;  /* float32 [N][N]: dL/dN(rho); the background enters before the
+                           resampling, so this is the sum over positions of the
+                           pulled-back dL/dI' (Eq. 1's common background, Fig. 1B) */
 } ptycho_grads_t;
 
 /* Adam state and hyper-parameters, one per job (real and imaginary parts
    are independent coordinates).  m_* / v_* have the shapes of the variables
-   (complex arrays as interleaved floats).  A NULL m/v pair or a zero learning
-   rate leaves that variable unchanged.  t is the 1-based step number used
-   for bias correction. */
+   (complex arrays as interleaved floats).  A zero learning rate leaves that
+   variable unchanged; a non-zero one needs its m/v pair and its gradient
+   output (and, for sigma and background, the job's array).  t is the
+   1-based step number used for bias correction.  The paper optimises all of
+   these variables with Adam (Section "Universal Ptychography Algorithm
+   based on Automatic Differentiation"). */
 typedef struct ptycho_adam {
   float *m_object, *v_object, *m_probe, *v_probe, *m_pos, *v_pos;
   float lr_object, lr_probe, lr_pos;
   float beta1, beta2, eps;
   int32_t t;
+  float *m_sigma, *v_sigma, *m_background, *v_background;
+  float lr_sigma, lr_background;
 } ptycho_adam_t;
 
 /* Returns 1 if window N with DFT size pad is compiled in, else 0. */
@@ -173,8 +183,8 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
                          const ptycho_grads_t* grads, void* workspace, size_t workspace_bytes,
                          void* stream);
 
-/* Loss, gradients and one Adam update of object, probe and positions of each
-   job, in place.  grads[j].g_* must be non-NULL for every variable whose
+/* Loss, gradients and one Adam update of object, probe, positions, power
+   coefficients and background of each job, in place.  grads[j].g_* must be non-NULL for every variable whose
    learning rate is non-zero (they receive the gradient at the state before
    the update). */
 int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_t* loss,

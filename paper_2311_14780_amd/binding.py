@@ -52,7 +52,7 @@ class LossT(ctypes.Structure):
 
 class GradsT(ctypes.Structure):
     _fields_ = [("loss", _c_p), ("g_object", _c_p), ("g_probe", _c_p), ("g_pos", _c_p),
-                ("g_sigma", _c_p)]
+                ("g_sigma", _c_p), ("g_background", _c_p)]
 
 
 class AdamT(ctypes.Structure):
@@ -60,7 +60,9 @@ class AdamT(ctypes.Structure):
                 ("m_pos", _c_p), ("v_pos", _c_p), ("lr_object", ctypes.c_float),
                 ("lr_probe", ctypes.c_float), ("lr_pos", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("t", _c_i32)]
+                ("t", _c_i32), ("m_sigma", _c_p), ("v_sigma", _c_p), ("m_background", _c_p),
+                ("v_background", _c_p), ("lr_sigma", ctypes.c_float),
+                ("lr_background", ctypes.c_float)]
 
 
 class PtychoError(RuntimeError):
@@ -251,6 +253,7 @@ def _grads_array(grads: Sequence[dict]):
         arr[i].g_probe = _ptr(g.get("g_probe"))
         arr[i].g_pos = _ptr(g.get("g_pos"))
         arr[i].g_sigma = _ptr(g.get("g_sigma"))
+        arr[i].g_background = _ptr(g.get("g_background"))
     return arr
 
 
@@ -274,9 +277,14 @@ def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequen
         arr[i].m_object, arr[i].v_object = _ptr(a.get("m_object")), _ptr(a.get("v_object"))
         arr[i].m_probe, arr[i].v_probe = _ptr(a.get("m_probe")), _ptr(a.get("v_probe"))
         arr[i].m_pos, arr[i].v_pos = _ptr(a.get("m_pos")), _ptr(a.get("v_pos"))
+        arr[i].m_sigma, arr[i].v_sigma = _ptr(a.get("m_sigma")), _ptr(a.get("v_sigma"))
+        arr[i].m_background = _ptr(a.get("m_background"))
+        arr[i].v_background = _ptr(a.get("v_background"))
         arr[i].lr_object = float(a.get("lr_object", 0.0))
         arr[i].lr_probe = float(a.get("lr_probe", 0.0))
         arr[i].lr_pos = float(a.get("lr_pos", 0.0))
+        arr[i].lr_sigma = float(a.get("lr_sigma", 0.0))
+        arr[i].lr_background = float(a.get("lr_background", 0.0))
         arr[i].beta1 = float(a.get("beta1", 0.9))
         arr[i].beta2 = float(a.get("beta2", 0.999))
         arr[i].eps = float(a.get("eps", 1e-8))

@@ -318,7 +318,28 @@ int round_chunk(int C, int K, int group) {
 bool wants_adjoint(const Call& c, int i) {
   if (c.which == 0) return false;
   const ptycho_grads_t& g = c.grads[i];
-  return g.g_object || g.g_probe || g.g_pos || g.g_sigma;
+  return g.g_object || g.g_probe || g.g_pos || g.g_sigma || g.g_background;
+}
+
+// Floats of variable v (0 object, 1 probe, 2 positions, 3 sigma, 4 background).
+size_t var_floats(const ptycho_job_t& j, int v) {
+  switch (v) {
+    case 0: return 2ull * j.L * j.H * j.W;
+    case 1: return 2ull * j.L * j.M * j.N * j.N;
+    case 2: return 2ull * j.K;
+    case 3: return static_cast<size_t>(j.K);
+    default: return static_cast<size_t>(j.N) * j.N;
+  }
+}
+
+float* grad_of(const ptycho_grads_t& g, int v) {
+  float* const p[kVars] = {g.g_object, g.g_probe, g.g_pos, g.g_sigma, g.g_background};
+  return p[v];
+}
+
+float adam_lr(const ptycho_adam_t& a, int v) {
+  const float lr[kVars] = {a.lr_object, a.lr_probe, a.lr_pos, a.lr_sigma, a.lr_background};
+  return lr[v];
 }
 
 int layout(Call& c, void* ws, size_t ws_bytes) {
@@ -430,18 +451,19 @@ void fill_job(Call& c, int i, char** cursor) {
     d.g_probe = reinterpret_cast<float2*>(g.g_probe);
     d.g_pos = g.g_pos;
     d.g_sigma = g.g_sigma;
+    d.g_background = g.g_background;
   }
   d.var_flat[0] = j.object;
   d.var_flat[1] = j.probe;
   d.var_flat[2] = j.pos;
+  d.var_flat[3] = j.sigma;
+  d.var_flat[4] = j.background;
   d.grad_flat[0] = reinterpret_cast<float*>(d.g_object);
   d.grad_flat[1] = reinterpret_cast<float*>(d.g_probe);
   d.grad_flat[2] = d.g_pos;
   d.grad_flat[3] = d.g_sigma;
-  d.flat_n[0] = 2LL * j.L * j.H * j.W;
-  d.flat_n[1] = 2LL * j.L * j.M * j.N * j.N;
-  d.flat_n[2] = 2LL * j.K;
-  d.flat_n[3] = j.K;
+  d.grad_flat[4] = d.g_background;
+  for (int v = 0; v < kVars; ++v) d.flat_n[v] = static_cast<long long>(var_floats(j, v));
   d.out = c.out ? c.out[i] : nullptr;
   d.status = c.status + i;
   d.loss_k = c.loss_k[i];
@@ -472,15 +494,13 @@ void fill_job(Call& c, int i, char** cursor) {
   d.probe_group = c.pgroup[i];
   if (c.adam) {
     const ptycho_adam_t& a = c.adam[i];
-    d.adam_m[0] = a.m_object;
-    d.adam_v[0] = a.v_object;
-    d.adam_m[1] = a.m_probe;
-    d.adam_v[1] = a.v_probe;
-    d.adam_m[2] = a.m_pos;
-    d.adam_v[2] = a.v_pos;
-    d.adam_lr[0] = a.lr_object;
-    d.adam_lr[1] = a.lr_probe;
-    d.adam_lr[2] = a.lr_pos;
+    float* const m[kVars] = {a.m_object, a.m_probe, a.m_pos, a.m_sigma, a.m_background};
+    float* const v[kVars] = {a.v_object, a.v_probe, a.v_pos, a.v_sigma, a.v_background};
+    for (int q = 0; q < kVars; ++q) {
+      d.adam_m[q] = m[q];
+      d.adam_v[q] = v[q];
+      d.adam_lr[q] = adam_lr(a, q);
+    }
     d.adam_beta1 = a.beta1;
     d.adam_beta2 = a.beta2;
     d.adam_eps = a.eps;
@@ -534,16 +554,10 @@ int run_prologue(Call& c, hipStream_t s) {
   Phase ph;
   auto zero = ph.begin();
   if (c.grads) {
-    for (int i = 0; i < c.n; ++i) {
-      const ptycho_job_t& j = c.jobs[i];
-      const ptycho_grads_t& g = c.grads[i];
-      const size_t sizes[4] = {2ull * j.L * j.H * j.W, 2ull * j.L * j.M * j.N * j.N, 2ull * j.K,
-                               static_cast<size_t>(j.K)};
-      const bool want[4] = {g.g_object != nullptr, g.g_probe != nullptr, g.g_pos != nullptr,
-                            g.g_sigma != nullptr};
-      for (int a = 0; a < 4; ++a)
-        if (want[a]) ph.add(zero, i, a, static_cast<long long>((sizes[a] + 1023) / 1024));
-    }
+    for (int i = 0; i < c.n; ++i)
+      for (int v = 0; v < kVars; ++v)
+        if (grad_of(c.grads[i], v))
+          ph.add(zero, i, v, static_cast<long long>((var_floats(c.jobs[i], v) + 1023) / 1024));
   }
   auto stat = ph.begin();
   for (int i = 0; i < c.n; ++i) ph.add(stat, i, 0, 1);
@@ -627,6 +641,12 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
       for (int l = 0; l < j.L; ++l) ph.add(obj, members[q], l, tiles);
     }
   }
+  auto bgr = ph.begin();
+  if (key.adjoint) {
+    const long long nblk = static_cast<long long>((plane + 255) / 256);
+    for (size_t q = 0; q < members.size(); ++q)
+      if (cnt[q] && c.grads[members[q]].g_background) ph.add(bgr, members[q], 0, nblk);
+  }
   auto fin = ph.begin();
   if (c.which != 0)
     for (size_t q = 0; q < members.size(); ++q) ph.add(fin, members[q], 0, (cnt[q] + 63) / 64);
@@ -654,6 +674,8 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     }
   }
   if (key.adjoint) {
+    // background gradient: before the column adjoint reuses GX
+    LAUNCH(KC_FINALIZE, launch_simple(KBgReduce, launch_of(c, bgr, iter), bgr.units, s));
     for (size_t p = 0; p < nls.size(); ++p) {
       size_t lds = 0;  // the launch's largest probe-gradient accumulator
       bool grouped = false;
@@ -684,14 +706,10 @@ int run_epilogue(Call& c, hipStream_t s) {
     if (c.grads[i].loss) ph.add(tot, i, 0, 1);
   auto ad = ph.begin();
   if (c.adam) {
-    for (int i = 0; i < c.n; ++i) {
-      const ptycho_job_t& j = c.jobs[i];
-      const ptycho_adam_t& a = c.adam[i];
-      const size_t sizes[3] = {2ull * j.L * j.H * j.W, 2ull * j.L * j.M * j.N * j.N, 2ull * j.K};
-      const float lrs[3] = {a.lr_object, a.lr_probe, a.lr_pos};
-      for (int v = 0; v < 3; ++v)
-        if (lrs[v] != 0.f) ph.add(ad, i, v, static_cast<long long>((sizes[v] + 1023) / 1024));
-    }
+    for (int i = 0; i < c.n; ++i)
+      for (int v = 0; v < kVars; ++v)
+        if (adam_lr(c.adam[i], v) != 0.f)
+          ph.add(ad, i, v, static_cast<long long>((var_floats(c.jobs[i], v) + 1023) / 1024));
   }
   int e = upload_phase(c, ph, s);
   if (e) return e;
@@ -738,13 +756,15 @@ int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
   return run_epilogue(c, s);
 }
 
+// Argument checks shared by the entry points (host only, nothing touches
+// the device); each entry point calls init_twiddles() after all its checks.
 int common_checks(const ptycho_job_t* jobs, int n_jobs, bool need_measured) {
   if (!jobs || n_jobs < 1) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i) {
     const int e = validate_job(jobs[i], need_measured);
     if (e) return e;
   }
-  return init_twiddles();
+  return PTYCHO_OK;
 }
 
 }  // namespace
@@ -783,6 +803,8 @@ int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* i
   if (!intensity || !workspace) return PTYCHO_EINVAL;
   for (int i = 0; i < n_jobs; ++i)
     if (jobs[i].K > 0 && !intensity[i]) return PTYCHO_EINVAL;
+  e = init_twiddles();
+  if (e) return e;
   Call c;
   c.which = 0;
   c.n = n_jobs;
@@ -802,6 +824,8 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
   if (!loss || !grads || !workspace) return PTYCHO_EINVAL;
   if (loss->kind < 0 || loss->kind > 3 || !(loss->eps >= 0.f) || !std::isfinite(loss->scale))
     return PTYCHO_EINVAL;
+  e = init_twiddles();
+  if (e) return e;
   Call c;
   c.which = 1;
   c.n = n_jobs;
@@ -829,7 +853,14 @@ int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_
     if (a.lr_object != 0.f && (!a.m_object || !a.v_object || !grads[i].g_object)) return PTYCHO_EINVAL;
     if (a.lr_probe != 0.f && (!a.m_probe || !a.v_probe || !grads[i].g_probe)) return PTYCHO_EINVAL;
     if (a.lr_pos != 0.f && (!a.m_pos || !a.v_pos || !grads[i].g_pos)) return PTYCHO_EINVAL;
+    if (a.lr_sigma != 0.f && (!a.m_sigma || !a.v_sigma || !grads[i].g_sigma || !jobs[i].sigma))
+      return PTYCHO_EINVAL;
+    if (a.lr_background != 0.f &&
+        (!a.m_background || !a.v_background || !grads[i].g_background || !jobs[i].background))
+      return PTYCHO_EINVAL;
   }
+  e = init_twiddles();
+  if (e) return e;
   Call c;
   c.which = 2;
   c.n = n_jobs;

@@ -542,6 +542,9 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
       }
       lsum += wt * ell;
       acc[e] = loss.gscale * wt * dell;  // 2 * scale * w * dloss/dI
+      // background gradient terms, summed over positions by k_bg_reduce
+      if (MODE == 0 && jb.g_background)
+        gmem(reinterpret_cast<float*>(jb.GX))[static_cast<size_t>(c) * plane + pix] = acc[e];
     }
     if (MODE == 1) return;
     const float s = block_sum(lsum, red);
@@ -850,6 +853,26 @@ __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   const int PG = jb.probe_group;  // one summed term per group of positions
   for (int c = 0; c < C; c += PG) acc = cadd(acc, ldv(src, c * stride));
   stv(gp, static_cast<size_t>(lm) * plane + pix, acc);
+}
+
+// --------------------------------------- background gradient: ordered k sum
+// g_background[pix] += sum over the chunk's positions, ascending, of
+// (1/2) (2 scale w dL/dI')-pulled-back: from the resampling buffer (after
+// R^T) or from the detector kernel's terms parked in GX.
+// units: pixel blocks of NT per job
+__global__ __launch_bounds__(NT) void k_bg_reduce(Launch la) {
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*gmem(jb.status)) return;
+  const size_t plane = static_cast<size_t>(jb.N) * jb.N;
+  const size_t pix = static_cast<size_t>(r.u) * NT + threadIdx.x;
+  if (pix >= plane) return;
+  const gf32* __restrict__ src = gmem(jb.ibuf ? jb.ibuf : reinterpret_cast<const float*>(jb.GX)) + pix;
+  gf32* __restrict__ gb = gmem(jb.g_background);
+  float acc = gb[pix];
+  const int C = min(jb.C, jb.K - la.iter * jb.C);
+  for (int c = 0; c < C; ++c) acc += 0.5f * src[static_cast<size_t>(c) * plane];
+  gb[pix] = acc;
 }
 
 // -------------------------------------------------------------- row adjoint
@@ -1165,6 +1188,7 @@ hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_
     case KFinalize: hipLaunchKernelGGL(k_finalize_chunk, grid1(units), dim3(64), 0, s, la); break;
     case KAdam: hipLaunchKernelGGL(k_adam, grid1(units), dim3(NT), 0, s, la); break;
     case KCztTables: hipLaunchKernelGGL(k_czt_tables, grid1(units), dim3(NT), 0, s, la); break;
+    case KBgReduce: hipLaunchKernelGGL(k_bg_reduce, grid1(units), dim3(NT), 0, s, la); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

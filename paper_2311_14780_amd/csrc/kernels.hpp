@@ -8,6 +8,7 @@
 namespace ptycho {
 
 constexpr int kMaxL = 8;
+constexpr int kVars = 5;  // object, probe, positions, sigma, background
 
 // One job of a call, as seen by the kernels (kept in device memory; every
 // launch reads it through the job index of its work segments).
@@ -41,6 +42,7 @@ struct JobDev {
   float2* g_probe;
   float* g_pos;
   float* g_sigma;
+  float* g_background;  // [N][N]
   float* out;           // forward intensities [K][N][N]
   // workspace of this job for one chunk of C positions
   int* status;
@@ -48,7 +50,9 @@ struct JobDev {
   float2* ramp;         // [C][2][N]    exp(+2 pi i f delta), y then x
   float2* X;            // [C][L][N][N] row-shifted patch, later G_A
   float2* Y;            // [C][L][M][N][N] column DFT -> Psi -> Z -> probe-gradient terms
-  float2* GX;           // [C][L][N][N] gradient after the adjoint column shift
+  float2* GX;           // [C][L][N][N] gradient after the adjoint column shift; between
+                        // the detector kernel and the column adjoint its first C N^2
+                        // floats hold 2 scale w dL/dI per position (background gradient)
   float* loss_part;     // [C][n_loss]
   float* dy_part;       // [C][L][N / G]
   float* sg_part;       // [C][L][N / G]
@@ -60,18 +64,18 @@ struct JobDev {
   int want_adjoint;
   int probe_group;      // positions whose probe-gradient terms one column-adjoint
                         // block sums in LDS (1: one term per position)
-  // Flat float views selected by a segment's l in the gradient-zeroing
-  // (0 object, 1 probe, 2 positions, 3 sigma) and Adam (0..2) launches.
+  // Flat float views selected by a segment's l in the gradient-zeroing and
+  // Adam launches (0 object, 1 probe, 2 positions, 3 sigma, 4 background).
   // The host fills them so that those kernels pick their arrays by index:
   // a multi-way branch on l that assigns pointers was compiled into code
   // that left the pointer registers of the later cases unset.
-  float* var_flat[3];     // object, probe, positions
-  float* grad_flat[4];    // g_object, g_probe, g_pos, g_sigma (may be null)
-  long long flat_n[4];    // floats in each of the four
+  float* var_flat[kVars];
+  float* grad_flat[kVars];  // may be null
+  long long flat_n[kVars];  // floats in each
   // Adam (ptycho_step)
-  float* adam_m[3];
-  float* adam_v[3];
-  float adam_lr[3];
+  float* adam_m[kVars];
+  float* adam_v[kVars];
+  float adam_lr[kVars];
   float adam_beta1, adam_beta2, adam_eps, adam_bc1, adam_bc2;
 };
 static_assert(sizeof(JobDev) % sizeof(int) == 0, "the table writer copies whole ints");
@@ -107,7 +111,8 @@ struct TablePayload {
 
 // Kinds of the simple launches (launch_simple).
 enum SimpleKind {
-  KZeroGrads, KSetStatus, KValidate, KPrep, KProbeReduce, KObjGather, KFinalize, KAdam, KCztTables
+  KZeroGrads, KSetStatus, KValidate, KPrep, KProbeReduce, KObjGather, KFinalize, KAdam, KCztTables,
+  KBgReduce
 };
 // Blocks of k_czt_tables per (job, wavelength) with the exact-ratio propagator.
 int czt_table_blocks(int N);

@@ -203,3 +203,22 @@ def test_ratio_ignores_pad_and_workspace_holds_the_chirp_tables():
     assert got == b
     # an integer-valued ratio is still the exact-ratio propagator
     assert _ws_bytes(_job_ratio((64.0, 0.0), K=8), chunk=4)[1] > ref
+
+
+def test_grads_and_adam_struct_layout():
+    assert B.GradsT.g_background.offset == 5 * 8
+    # six pointers, six floats, t, then the sigma / background extension
+    assert B.AdamT.t.offset == 72
+    assert B.AdamT.m_sigma.offset == 80
+    assert B.AdamT.lr_background.offset == 80 + 32 + 4
+
+
+def test_adam_of_sigma_needs_its_state():
+    j = _job()
+    loss = B.LossT(0, 1e-6, 1.0)
+    grads = B.GradsT()
+    adam = B.AdamT()
+    adam.t, adam.beta1, adam.beta2, adam.lr_sigma = 1, 0.9, 0.999, 1e-3
+    rc = B.lib().ptycho_step(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                             ctypes.byref(adam), ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == B.PTYCHO_EINVAL

@@ -93,7 +93,7 @@ def test_exact_ratio_chunking_and_mixed_calls_are_bitwise_invariant():
     pr, pp = U.to_problem(case_r, DEV), U.to_problem(case_p, DEV)
     whole = U.gpu_grads(pr)
     part = U.gpu_grads(pr, chunk=4)
-    for k in ("loss", "g_object", "g_probe", "g_pos", "g_sigma"):
+    for k in ("loss", "g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
         assert np.array_equal(np.asarray(whole[k]), np.asarray(part[k])), k
     # both jobs in one call: each equals its single-job result bitwise
     alone_p = U.gpu_grads(pp)
@@ -101,11 +101,12 @@ def test_exact_ratio_chunking_and_mixed_calls_are_bitwise_invariant():
     for p in (pr, pp):
         gs.append(dict(loss=torch.zeros(1, device=DEV), g_object=torch.zeros_like(p.object),
                        g_probe=torch.zeros_like(p.probe), g_pos=torch.zeros(p.K, 2, device=DEV),
-                       g_sigma=torch.zeros(p.K, device=DEV)))
+                       g_sigma=torch.zeros(p.K, device=DEV),
+                       g_background=torch.zeros(p.N, p.N, device=DEV)))
     ws = B.workspace([pr, pp], 1)
     B.ptycho_loss_grad([pr, pp], gs, workspace=ws)
     torch.cuda.synchronize()
     for g, ref in ((gs[0], whole), (gs[1], alone_p)):
-        for k in ("g_object", "g_probe", "g_pos"):
+        for k in ("g_object", "g_probe", "g_pos", "g_background"):
             assert np.array_equal(g[k].cpu().numpy(), ref[k]), k
         assert float(g["loss"].cpu()[0]) == ref["loss"]

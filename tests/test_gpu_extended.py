@@ -83,6 +83,36 @@ def test_adam_step_updates_state():
     assert torch.allclose(adam["m_pos"], 0.1 * g["g_pos"].reshape(-1), rtol=1e-6, atol=0)
 
 
+def test_adam_step_updates_sigma_and_background():
+    # the power coefficients and the common background are variables too
+    from paper_2311_14780_amd import binding as B
+    w = synth.reduced(synth.get_workload("C1"), L=2, M=2, harmonics=(19, 23),
+                      mode_weights=(0.75, 0.25), K=10, name="C1sb")
+    case = U.make_case(w, with_sigma=True, with_bg=True, with_mask=True, pads=(80, 64))
+    prob = U.to_problem(case, DEV)
+    sg0, bg0 = prob.sigma.clone(), prob.background.clone()
+    g = dict(loss=torch.zeros(1, device=DEV), g_sigma=torch.zeros(prob.K, device=DEV),
+             g_background=torch.zeros(prob.N, prob.N, device=DEV))
+    z = lambda x: torch.zeros(x.numel(), device=DEV)
+    adam = dict(m_sigma=z(sg0), v_sigma=z(sg0), m_background=z(bg0), v_background=z(bg0),
+                lr_sigma=5e-3, lr_background=2e-2, t=1)
+    ws = B.workspace([prob], 2)
+    B.ptycho_step([prob], [g], [adam], kind=1, workspace=ws)
+    torch.cuda.synchronize()
+    ref = U.oracle_grads(case, kind=1)
+    got = {"loss": float(g["loss"].item()), "g_sigma": g["g_sigma"].cpu().numpy(),
+           "g_background": g["g_background"].cpu().numpy()}
+    print("sigma/background grads", U.compare(got, ref, keys=("g_sigma", "g_background")))
+    for x0, x1, gg, lr in ((sg0, prob.sigma, g["g_sigma"], 5e-3),
+                           (bg0, prob.background, g["g_background"], 2e-2)):
+        gr = gg.cpu().numpy().astype(np.float64).ravel()
+        want = -lr * gr / (np.abs(gr) + 1e-8)  # first Adam step: -lr sign(g)
+        d_got = (x1.cpu().numpy().astype(np.float64) - x0.cpu().numpy()).ravel()
+        assert U.rel_l2(d_got, want) <= 1e-4
+    # object, probe and positions were left alone (zero learning rates)
+    assert torch.equal(prob.object, torch.from_numpy(case["obj"]).to(DEV))
+
+
 def test_autograd_loss_matches_direct_call_and_differences():
     from paper_2311_14780_amd import autograd as A
     case = U.make_case(synth.reduced(synth.get_workload("C1"), K=8, name="C1g"))

@@ -73,7 +73,7 @@ def test_chunking_is_bitwise_invariant(c1):
     prob = U.to_problem(c1, DEV)
     a = U.gpu_grads(prob, chunk=0)
     b = U.gpu_grads(prob, chunk=7)
-    for k in ("loss", "g_object", "g_probe", "g_pos", "g_sigma"):
+    for k in ("loss", "g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
 
 
@@ -86,13 +86,14 @@ def test_multi_job_call_matches_single_jobs(c1):
     for p in (p1, p2):
         gs.append(dict(loss=torch.zeros(1, device=DEV), g_object=torch.zeros_like(p.object),
                        g_probe=torch.zeros_like(p.probe), g_pos=torch.zeros(p.K, 2, device=DEV),
-                       g_sigma=torch.zeros(p.K, device=DEV)))
+                       g_sigma=torch.zeros(p.K, device=DEV),
+                       g_background=torch.zeros(p.N, p.N, device=DEV)))
     ws = B.workspace([p1, p2])
     B.ptycho_loss_grad([p1, p2], gs, workspace=ws)
     torch.cuda.synchronize()
     for single, g in ((s1, gs[0]), (s2, gs[1])):
         assert single["loss"] == float(g["loss"].item())
-        for k in ("g_object", "g_probe", "g_pos", "g_sigma"):
+        for k in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
             assert np.array_equal(single[k], g[k].cpu().numpy()), k
 
 
