@@ -116,6 +116,22 @@ def propagate(psi: np.ndarray, nl) -> np.ndarray:
     return F[np.ix_(idx, idx)]
 
 
+def scaled_dft_matrix_dalpha(N: int, alpha: float) -> np.ndarray:
+    """d/d alpha of ``scaled_dft_matrix``: F[j, r] (-1/(2 alpha) + 2 pi i u_j r / alpha^2)."""
+    u = np.arange(N, dtype=np.float64) - N // 2
+    r = np.arange(N, dtype=np.float64)
+    E = -0.5 / alpha + 2j * np.pi * np.outer(u, r) / alpha ** 2
+    return scaled_dft_matrix(N, alpha) * E
+
+
+def propagate_dalpha(psi: np.ndarray, alpha: float) -> np.ndarray:
+    """d Psi / d alpha of the exact-ratio propagator (product rule on F psi F^T)."""
+    N = psi.shape[-1]
+    F = scaled_dft_matrix(N, float(alpha))
+    dF = scaled_dft_matrix_dalpha(N, float(alpha))
+    return dF @ psi @ F.T + F @ psi @ dF.T
+
+
 def propagate_adjoint(G: np.ndarray, nl) -> np.ndarray:
     """Adjoint of ``propagate``: embed the bins, unitary inverse DFT, crop;
     for a float ``nl``, F^H G conj(F)."""
@@ -231,7 +247,10 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     Returns a dict: loss (float), g_object (shape of ``obj``), g_probe
     [L][M][N][N], g_pos [K][2], g_sigma [K] (zero outside the subset),
     g_background [N][N] (the background enters f5 before the resampling, so
-    its gradient is the sum over positions of the pulled-back dL/dI').
+    its gradient is the sum over positions of the pulled-back dL/dI'),
+    g_ratio [L] (dL/d alpha_l for exact-ratio wavelengths, 0 for zero-padded
+    ones; alpha_l is proportional to the propagation distance z, so
+    dL/dz = sum_l alpha_l / z * dL/d alpha_l).
     """
     obj, squeeze = _as_object(obj)
     probe = np.asarray(probe, dtype=np.complex128)
@@ -246,6 +265,7 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     g_pos = np.zeros((K, 2))
     g_sig = np.zeros(K)
     g_bg = np.zeros((N, N))
+    g_ratio = np.zeros(L)
     total = 0.0
     ks = range(K) if positions is None else positions
     for k in ks:
@@ -271,6 +291,10 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
                 for m in range(M):
                     # |Psi|^2 -> Psi: G_Psi = 2 g Psi; f4 adjoint
                     chi = propagate_adjoint(2.0 * g * Psi[l, n, m], pads[l])
+                    if is_ratio(pads[l]):
+                        # dL/d alpha_l = Re <G_Psi, dPsi/d alpha>
+                        dpsi = propagate_dalpha(sig * probe[l, m] * Osh[l, n], pads[l])
+                        g_ratio[l] += float(np.real(np.vdot(2.0 * g * Psi[l, n, m], dpsi)))
                     g_prb[l, m] += np.conj(sig * Osh[l, n]) * chi
                     G_osh += np.conj(sig * probe[l, m]) * chi
                     g_sig[k] += float(np.real(np.sum(np.conj(chi) * probe[l, m] * Osh[l, n])))
@@ -287,5 +311,7 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     g_pos *= scale
     g_sig *= scale
     g_bg *= scale
+    g_ratio *= scale
     return dict(loss=total * scale, g_object=g_obj[:, 0] if squeeze else g_obj,
-                g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig, g_background=g_bg)
+                g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig, g_background=g_bg,
+                g_ratio=g_ratio)

@@ -144,3 +144,44 @@ def test_zero_gradient_at_noiseless_truth_with_ratios():
     assert abs(r["loss"]) <= 1e-12 * np.sum(meas)
     for key in ("g_object", "g_probe", "g_pos"):
         assert np.max(np.abs(r[key])) < 1e-9, key
+
+
+def test_ratio_gradient_matches_central_differences():
+    # dL/d alpha_l: the propagation-distance gradient of the exact-ratio model
+    for kind in (om.LOSS_AMPLITUDE, om.LOSS_POISSON):
+        pr = tiny_problem(seed=23, L=2, M=2, pads=(9.41, 12.66), with_sigma=True,
+                          with_bg=True, with_table=True)
+        meas = _perturbed_measurement(pr)
+        kw = dict(kind=kind, eps=1e-3, scale=0.7, sigma=pr["sigma"], background=pr["bg"],
+                  resample_table=pr["table"])
+        base = om.loss_grad(pr["obj"], pr["prb"], pr["pos"], pr["pads"], meas, **kw)
+        h = 1e-5
+        for l in range(2):
+            up, dn = list(pr["pads"]), list(pr["pads"])
+            up[l] += h
+            dn[l] -= h
+            fd = (om.loss_grad(pr["obj"], pr["prb"], pr["pos"], tuple(up), meas, **kw)["loss"] -
+                  om.loss_grad(pr["obj"], pr["prb"], pr["pos"], tuple(dn), meas, **kw)["loss"]) / (2 * h)
+            an = base["g_ratio"][l]
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), (kind, l, fd, an)
+
+
+def test_ratio_gradient_is_zero_for_padded_wavelengths_and_at_truth():
+    pr = tiny_problem(seed=25, pads=(8, 10.37))
+    meas = om.forward(pr["obj"], pr["prb"], pr["pos"], pr["pads"])
+    r = om.loss_grad(pr["obj"], pr["prb"], pr["pos"], pr["pads"], meas)
+    assert r["g_ratio"][0] == 0.0
+    assert abs(r["g_ratio"][1]) < 1e-9
+    pr2 = tiny_problem(seed=25, pads=(8, 10.37))
+    meas2 = _perturbed_measurement(pr2)
+    r2 = om.loss_grad(pr2["obj"], pr2["prb"], pr2["pos"], pr2["pads"], meas2)
+    assert r2["g_ratio"][0] == 0.0 and abs(r2["g_ratio"][1]) > 1e-6
+
+
+def test_ratio_derivative_of_the_propagator_matches_differences():
+    N, a = 8, 11.3
+    psi = _rand(N, 9)
+    h = 1e-6
+    fd = (om.propagate(psi, a + h) - om.propagate(psi, a - h)) / (2 * h)
+    an = om.propagate_dalpha(psi, a)
+    assert np.max(np.abs(fd - an)) <= 1e-7 * np.max(np.abs(an))
