@@ -138,6 +138,14 @@ typedef struct ptycho_grads {
   float* g_background;  /* float32 [N][N]: dL/dN(rho); the background enters before the
                            resampling, so this is the sum over positions of the
                            pulled-back dL/dI' (Eq. 1's common background, Fig. 1B) */
+  float* g_ratio;       /* float32 [L]: dL/dalpha_l for the exact-ratio wavelengths (0 for
+                           zero-padded ones).  alpha_l = lambda_l z / (p dx) is proportional
+                           to the propagation distance z of D_{lambda,z}, so
+                           dL/dz = sum_l (alpha_l / z) dL/dalpha_l (the distance correction of
+                           Section "Benchmarking with state-of-art open-source ptychography
+                           algorithm").  Costs one extra row and one extra column transform
+                           per (position, wavelength, mode) and recomputes Psi in the
+                           adjoint. */
 } ptycho_grads_t;
 
 /* Adam state and hyper-parameters, one per job (real and imaginary parts

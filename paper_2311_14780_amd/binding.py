@@ -52,7 +52,7 @@ class LossT(ctypes.Structure):
 
 class GradsT(ctypes.Structure):
     _fields_ = [("loss", _c_p), ("g_object", _c_p), ("g_probe", _c_p), ("g_pos", _c_p),
-                ("g_sigma", _c_p), ("g_background", _c_p)]
+                ("g_sigma", _c_p), ("g_background", _c_p), ("g_ratio", _c_p)]
 
 
 class AdamT(ctypes.Structure):
@@ -254,6 +254,7 @@ def _grads_array(grads: Sequence[dict]):
         arr[i].g_pos = _ptr(g.get("g_pos"))
         arr[i].g_sigma = _ptr(g.get("g_sigma"))
         arr[i].g_background = _ptr(g.get("g_background"))
+        arr[i].g_ratio = _ptr(g.get("g_ratio"))
     return arr
 
 

@@ -224,6 +224,11 @@ size_t czt_table_bytes(const ptycho_job_t& j) {
                     : 0;
 }
 
+// Per-position dL/d alpha_l ([K][L] float64) of a job with exact-ratio wavelengths.
+size_t ratio_k_bytes(const ptycho_job_t& j) {
+  return any_czt(j) ? align_up(std::max<size_t>(j.K, 1) * j.L * sizeof(double)) : 0;
+}
+
 int n_loss_of(const ptycho_job_t& j) {
   const int plane = j.N * j.N;
   return has_resample(j) ? (plane + 255) / 256 : j.N / rows_per_det_block(j.N);
@@ -242,6 +247,10 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
     b += align_up(static_cast<size_t>(n_loss_of(j)) * sizeof(float));
     b += 2 * align_up(L * (N / col_group_of(j.N)) * sizeof(float));  // dy, sigma
     b += align_up(L * (N / rows_per_adj_block(j.N)) * sizeof(float));  // dx
+    if (any_czt(j)) {  // alpha-derivative terms
+      b += align_up(L * (N / rows_per_det_block(j.N)) * sizeof(float));
+      b += align_up(L * (N / col_group_of(j.N)) * sizeof(float));
+    }
   }
   if (has_resample(j)) b += 2 * align_up(plane * sizeof(float));  // ibuf, gbuf
   return b;
@@ -254,7 +263,7 @@ size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
   b += align_up(sizeof(JobDev) * n_jobs);                           // job table
   b += align_up(sizeof(Seg) * static_cast<size_t>(kSegsPerJob) * n_jobs);  // segment pool
   for (int i = 0; i < n_jobs; ++i) b += align_up(std::max<size_t>(jobs[i].K, 1) * sizeof(double));
-  for (int i = 0; i < n_jobs; ++i) b += czt_table_bytes(jobs[i]);
+  for (int i = 0; i < n_jobs; ++i) b += czt_table_bytes(jobs[i]) + ratio_k_bytes(jobs[i]);
   return b;
 }
 
@@ -262,13 +271,17 @@ size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
 // `wide` (some wavelength uses the exact-ratio propagator) selects the
 // detector-kernel instance, so it is part of the key: a job's instances never
 // depend on the other jobs of a call.
+// `ratio_grad` (dL/d alpha wanted for exact-ratio wavelengths) selects the
+// detector instance that recomputes Psi in the adjoint.
 struct GroupKey {
   int N;
   bool resample;
   bool adjoint;
   bool wide;
+  bool ratio_grad;
   bool operator<(const GroupKey& o) const {
-    return std::tie(N, resample, adjoint, wide) < std::tie(o.N, o.resample, o.adjoint, o.wide);
+    return std::tie(N, resample, adjoint, wide, ratio_grad) <
+           std::tie(o.N, o.resample, o.adjoint, o.wide, o.ratio_grad);
   }
 };
 
@@ -287,7 +300,8 @@ struct Call {
   JobDev* jobs_dev = nullptr;
   Seg* seg_pool = nullptr;
   std::vector<double*> loss_k;
-  std::vector<char*> czt_tab;  // per job, or null
+  std::vector<char*> czt_tab;    // per job, or null
+  std::vector<double*> ratio_k;  // per job, or null
   char* chunk_base = nullptr;
   size_t chunk_bytes = 0;
   std::vector<JobDev> host_jobs;
@@ -318,7 +332,12 @@ int round_chunk(int C, int K, int group) {
 bool wants_adjoint(const Call& c, int i) {
   if (c.which == 0) return false;
   const ptycho_grads_t& g = c.grads[i];
-  return g.g_object || g.g_probe || g.g_pos || g.g_sigma || g.g_background;
+  return g.g_object || g.g_probe || g.g_pos || g.g_sigma || g.g_background || g.g_ratio;
+}
+
+// dL/d alpha wanted, and the job has exact-ratio wavelengths
+bool wants_ratio(const Call& c, int i) {
+  return c.which != 0 && c.grads[i].g_ratio != nullptr && any_czt(c.jobs[i]);
 }
 
 // Floats of variable v (0 object, 1 probe, 2 positions, 3 sigma, 4 background).
@@ -357,10 +376,14 @@ int layout(Call& c, void* ws, size_t ws_bytes) {
     p += align_up(std::max<size_t>(c.jobs[i].K, 1) * sizeof(double));
   }
   c.czt_tab.assign(c.n, nullptr);
+  c.ratio_k.assign(c.n, nullptr);
   for (int i = 0; i < c.n; ++i) {
     const size_t tb = czt_table_bytes(c.jobs[i]);
     if (tb) c.czt_tab[i] = p;
     p += tb;
+    const size_t rb = ratio_k_bytes(c.jobs[i]);
+    if (rb) c.ratio_k[i] = reinterpret_cast<double*>(p);
+    p += rb;
   }
   if (p > end) return PTYCHO_ENOSPC;
   c.chunk_base = p;
@@ -452,6 +475,7 @@ void fill_job(Call& c, int i, char** cursor) {
     d.g_pos = g.g_pos;
     d.g_sigma = g.g_sigma;
     d.g_background = g.g_background;
+    d.g_ratio = g.g_ratio;
   }
   d.var_flat[0] = j.object;
   d.var_flat[1] = j.probe;
@@ -464,6 +488,9 @@ void fill_job(Call& c, int i, char** cursor) {
   d.grad_flat[3] = d.g_sigma;
   d.grad_flat[4] = d.g_background;
   for (int v = 0; v < kVars; ++v) d.flat_n[v] = static_cast<long long>(var_floats(j, v));
+  d.grad_flat[kVars] = d.g_ratio;
+  d.flat_n[kVars] = j.L;
+  d.ratio_k = c.ratio_k[i];
   d.out = c.out ? c.out[i] : nullptr;
   d.status = c.status + i;
   d.loss_k = c.loss_k[i];
@@ -483,6 +510,10 @@ void fill_job(Call& c, int i, char** cursor) {
     d.dy_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
     d.sg_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
     d.dx_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_adj_block(j.N)) * sizeof(float)));
+    if (any_czt(j)) {
+      d.ra_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_det_block(j.N)) * sizeof(float)));
+      d.rb_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
+    }
   }
   if (has_resample(j)) {
     d.ibuf = reinterpret_cast<float*>(take(C * plane * sizeof(float)));
@@ -554,10 +585,12 @@ int run_prologue(Call& c, hipStream_t s) {
   Phase ph;
   auto zero = ph.begin();
   if (c.grads) {
-    for (int i = 0; i < c.n; ++i)
+    for (int i = 0; i < c.n; ++i) {
       for (int v = 0; v < kVars; ++v)
         if (grad_of(c.grads[i], v))
           ph.add(zero, i, v, static_cast<long long>((var_floats(c.jobs[i], v) + 1023) / 1024));
+      if (c.grads[i].g_ratio) ph.add(zero, i, kVars, 1);
+    }
   }
   auto stat = ph.begin();
   for (int i = 0; i < c.n; ++i) ph.add(stat, i, 0, 1);
@@ -596,7 +629,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowf, members[q], l, cnt[q]);
   // distinct DFT sizes of the group, in first-seen order
   std::vector<int> nls;
-  const bool wide = key.wide;
+  const int var = key.ratio_grad ? 2 : (key.wide ? 1 : 0);
   for (int i : members) {
     for (int l = 0; l < c.jobs[i].L; ++l)
       if (std::find(nls.begin(), nls.end(), eff_pad(c.jobs[i], l)) == nls.end())
@@ -659,18 +692,18 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     LAUNCH(KC_COL_FWD, launch_col_fwd(N, nls[p], launch_of(c, colf[p], iter), colf[p].units, s));
   const Launch ldet = launch_of(c, det, iter);
   if (c.which == 0) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, wide, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, var, s));
     if (key.resample) LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, true, s));
     return PTYCHO_OK;
   }
   if (!key.resample) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, wide, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, var, s));
   } else {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, wide, s));
+    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, var, s));
     LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, false, s));
     if (key.adjoint) {
       LAUNCH(KC_RESAMPLE, launch_resample_T(N, ldet, det.units, s));
-      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, wide, s));
+      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, var, s));
     }
   }
   if (key.adjoint) {
@@ -688,7 +721,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         lds = std::max(lds, col_adj_lds_of(N, j.M, c.pgroup[members[q]]));
       }
       LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
-                                        grouped, s));
+                                        grouped, key.ratio_grad, s));
     }
     LAUNCH(KC_PROBE_REDUCE, launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
     LAUNCH(KC_ROW_ADJ, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));
@@ -703,7 +736,7 @@ int run_epilogue(Call& c, hipStream_t s) {
   Phase ph;
   auto tot = ph.begin();
   for (int i = 0; i < c.n; ++i)
-    if (c.grads[i].loss) ph.add(tot, i, 0, 1);
+    if (c.grads[i].loss || c.grads[i].g_ratio) ph.add(tot, i, 0, 1);
   auto ad = ph.begin();
   if (c.adam) {
     for (int i = 0; i < c.n; ++i)
@@ -724,7 +757,8 @@ int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
   // groups of jobs sharing every kernel instance
   std::map<GroupKey, std::vector<int>> groups;
   for (int i = 0; i < c.n; ++i)
-    groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i), any_czt(c.jobs[i])}]
+    groups[GroupKey{c.jobs[i].N, has_resample(c.jobs[i]), wants_adjoint(c, i), any_czt(c.jobs[i]),
+                    wants_ratio(c, i)}]
         .push_back(i);
   c.chunk.assign(c.n, 1);
   c.pgroup.assign(c.n, 1);

@@ -126,6 +126,7 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 
 __device__ __forceinline__ int col_group_of_dev(int N) { return N <= 256 ? 16 : 8; }
 __device__ __forceinline__ int rb_adj_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
+__device__ __forceinline__ int rb_det_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 
 // ------------------------------------------------------- work decomposition
 // Largest s with segs[s].unit0 <= unit (segs sorted, segs[0].unit0 == 0).
@@ -469,15 +470,74 @@ __device__ __noinline__ void det_rows_adj_czt(lf2* buf, const lf32* acc, gf2* __
   fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld2, st2);
 }
 
+// Exact-ratio adjoint row pass that also returns this thread's share of the
+// detector-side terms of dL/d alpha (Y kept, Psi recomputed):
+//   Psi = F_x Y, Psi_s = F_x (s Y) (s the column index), G = g2 Psi,
+//   -(1/alpha) Re<G, Psi> + (2 pi / alpha^2) sum u_i Re(i conj(G) Psi_s)
+// (the x-axis factor and the normalisation of dPsi/d alpha), then
+// Z = F_x^H G written over Y.  psi: LDS [RB][N] holding Psi.
+template <int N, int NB, int RB>
+__device__ __noinline__ float det_rows_adj_czt_ratio(lf2* buf, lf2* psi, const lf32* acc,
+                                                     gf2* __restrict__ Yr,
+                                                     const gf2* __restrict__ twB,
+                                                     const gf2* __restrict__ tb, float inv_a,
+                                                     float c2) {
+  constexpr int LP = row_lp(NB);
+  using Ix = Lds<NB, LP, false>;
+  auto st_h = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmul(v, ldv(tb, 2 * N + t))); };
+  auto ld_b = [&](int line, int t) { return ldv(buf, Ix::at(line, t)); };
+  // Psi
+  auto ld_y = [&](int line, int t) {
+    return t < N ? cmul(ldv(Yr, line * N + t), ldv(tb, t)) : make_float2(0.f, 0.f);
+  };
+  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_y, st_h);
+  auto st_psi = [&](int line, int t, float2 v) {
+    if (t < N) stv(psi, line * N + t, cmul(v, ldv(tb, N + t)));
+  };
+  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_psi);
+  // Psi_s and the terms
+  auto ld_sy = [&](int line, int t) {
+    return t < N ? cscale(cmul(ldv(Yr, line * N + t), ldv(tb, t)), static_cast<float>(t))
+                 : make_float2(0.f, 0.f);
+  };
+  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_sy, st_h);
+  float ta = 0.f, tc = 0.f;
+  auto st_terms = [&](int line, int t, float2 v) {
+    if (t < N) {
+      const float2 ps = cmul(v, ldv(tb, N + t));
+      const float g2 = acc[line * N + t];
+      const float2 pv = ldv(psi, line * N + t);
+      const float2 G = cscale(pv, g2);
+      ta += g2 * cabs2(pv);
+      tc += static_cast<float>(t - N / 2) * (G.y * ps.x - G.x * ps.y);
+    }
+  };
+  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_terms);
+  // Z = F_x^H G over Y
+  auto ld_g = [&](int line, int t) {
+    return t < N ? cmulconj(ldv(tb, N + t), cscale(ldv(psi, line * N + t), acc[line * N + t]))
+                 : make_float2(0.f, 0.f);
+  };
+  auto st_hc = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmulconj(ldv(tb, 2 * N + t), v)); };
+  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_g, st_hc);
+  auto st_z = [&](int line, int t, float2 v) {
+    if (t < N) stv(Yr, line * N + t, cmulconj(ldv(tb, t), v));
+  };
+  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_z);
+  return c2 * tc - inv_a * ta;
+}
+
 // MODE 0: fused forward + loss + adjoint; 1: forward, write I + B to out;
 // 2: adjoint from g rows in the resampling buffer; 3: forward + loss only.
 // `spill` (MODE 1) writes Psi back over Y for a later MODE 2.
-// WIDE: the instance for launches with exact-ratio wavelengths (rows of 2N).
+// VAR 1: the instance for launches with exact-ratio wavelengths (rows of
+// 2N); VAR 2: as 1, for jobs that want dL/d alpha (the exact-ratio
+// wavelengths keep Y instead of Psi, and the adjoint recomputes Psi).
 // units: positions c
-template <int N, int MODE, bool WIDE>
+template <int N, int MODE, int VAR>
 __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill) {
   constexpr int RB = rb_det<N>();
-  using Rows = DetList<N, WIDE>;
+  using Rows = DetList<N, (VAR >= 1)>;
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
@@ -485,6 +545,9 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
   __shared__ float2 buf[RB * LPMAX];
   __shared__ float acc[RB * N];
   __shared__ float red[NT / 64];
+  __shared__ float2 psi[VAR == 2 ? RB * N : 1];
+  // exact-ratio wavelength whose alpha-derivative this call computes
+  auto ratio_l = [&](int l) { return VAR == 2 && jb.g_ratio != nullptr && jb.czt[l] != nullptr; };
   const int c = r.u, k = la.iter * jb.C + c, u0 = r.sub * RB;
   const int tid = threadIdx.x;
   const size_t plane = static_cast<size_t>(N) * N;
@@ -492,11 +555,12 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
   if (MODE != 2) {
     for (int e = tid; e < RB * N; e += NT) acc[e] = 0.f;
     __syncthreads();
-    const bool keep = (MODE == 0) || (MODE == 1 && spill);
     for (int l = 0; l < jb.L; ++l) {
       const float ps = jb.pad_scale[l];
       const float2* twL = jb.tw_pad[l];
       const int nl = jb.pad[l];
+      // Psi is kept for the adjoint, except where the adjoint recomputes it
+      const bool keep = ((MODE == 0) || (MODE == 1 && spill)) && !(jb.g_ratio && jb.czt[l]);
       for (int m = 0; m < jb.M; ++m) {
         gf2* Yr = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
                   static_cast<size_t>(u0) * N;
@@ -561,16 +625,31 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
     const float ps = jb.pad_scale[l];
     const float2* twL = jb.tw_pad[l];
     const int nl = jb.pad[l];
+    const bool rl = ratio_l(l);
+    float da = 0.f;  // this thread's share of the rows' dL/d alpha_l terms
     for (int m = 0; m < jb.M; ++m) {
       gf2* Yr = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
                 static_cast<size_t>(u0) * N;
       pad_switch(nl, [&](auto nlc) {
         constexpr int NL = decltype(nlc)::value;
-        if constexpr (NL == czt_nb<N>())
-          det_rows_adj_czt<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]));
-        else
+        if constexpr (NL == czt_nb<N>()) {
+          if (VAR == 2 && rl) {
+            const double a = jb.czt_alpha[l];
+            da += det_rows_adj_czt_ratio<N, NL, RB>(
+                (lf2*)buf, (lf2*)psi, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]),
+                static_cast<float>(1.0 / a), static_cast<float>(2.0 * kPi / (a * a)));
+          } else {
+            det_rows_adj_czt<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]));
+          }
+        } else {
           det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
+        }
       }, Rows{});
+    }
+    if (VAR == 2 && rl) {
+      const float sum = block_sum(da, red);
+      if (threadIdx.x == 0)
+        gmem(jb.ra_part)[(static_cast<size_t>(c) * jb.L + l) * (N / RB) + r.sub] = sum;
     }
   }
 }
@@ -662,7 +741,9 @@ __global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
 // instance for launches whose jobs all have groups of one: one position per
 // block, and the columns of mode m + 1 are loaded while mode m is processed
 // (too many registers on top of the group loop).
-template <int N, int NL, bool GROUPED>
+// RATIO: the exact-ratio instance that also computes the y-axis terms of
+// dL/d alpha (launches whose jobs want them).
+template <int N, int NL, bool GROUPED, bool RATIO>
 __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   constexpr int G = col_group<N>();
   const UnitRef r = decode<N / G>(la);
@@ -715,9 +796,12 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
 
   const float ps = jb.pad_scale[l];
   float sgsum = 0.f;
+  float rsum = 0.f;  // y-axis terms of dL/d alpha (exact ratio, g_ratio wanted)
   gf2* __restrict__ Z0 = gmem(jb.Y) + (static_cast<size_t>(c) * jb.L + l) * jb.M * N * N + x0;
   constexpr bool CZT = NL == czt_nb<N>();
   const gf2* __restrict__ tb = CZT ? gmem(jb.czt[l]) : nullptr;
+  static_assert(!RATIO || CZT, "alpha derivative of the exact-ratio propagator only");
+  const bool want_ratio = RATIO && jb.g_ratio != nullptr;
   // first-transform input of mode m at FFT index t: the cropped bins embedded
   // at their frequencies, or (exact ratio) conj(cout) Z in detector order
   auto zin_at = [&](const gf2* __restrict__ Zm, int line, int t) {
@@ -748,6 +832,24 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     auto st_chic = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cmulconj(ldv(tb, t), v);
     };
+    if constexpr (RATIO) {
+      if (want_ratio) {
+        // y-axis term of dL/d alpha: chi_u = F_y^H (u Z), summed against r psi
+        auto ld_u = [&](int line, int t) {
+          return cscale(zin_at(Z, line, t), static_cast<float>(t - N / 2));
+        };
+        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_u, st_hc);
+        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const int e = tid + q * CNT, line = e % G, i = e / G;
+          const float2 cu = buf[i * LP + line];
+          const float2 ps = cscale(cmul(ldv(P, i * N + line), o[q]), sig);
+          rsum += static_cast<float>(i) * (cu.y * ps.x - cu.x * ps.y);
+        }
+        __syncthreads();
+      }
+    }
     if constexpr (GROUPED) {
       auto ld_z = [&](int line, int t) { return zin_at(Z, line, t); };
       if constexpr (CZT) {
@@ -793,6 +895,13 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     const float s = block_sum<CNT>(sgsum, red);
     if (tid == 0)
       gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s;
+  }
+  if (want_ratio) {
+    const double a = jb.czt_alpha[l];
+    const float s = block_sum<CNT>(rsum, red);
+    if (tid == 0)
+      gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] =
+          static_cast<float>(2.0 * kPi / (a * a)) * s;
   }
   // Ghat = FFT_y(G_Osh): y-position derivative and adjoint y-shift
 #pragma unroll
@@ -1033,6 +1142,17 @@ __global__ void k_finalize_chunk(Launch la) {
     gmem(jb.g_pos)[2 * k + 1] = gx;
   }
   if (jb.g_sigma) gmem(jb.g_sigma)[k] = gs;
+  if (jb.g_ratio) {
+    const int n_ra = jb.N / rb_det_dev(jb.N);
+    for (int l = 0; l < jb.L; ++l) {
+      double da = 0.0;
+      if (jb.czt[l]) {
+        for (int i = 0; i < n_ra; ++i) da += gmem(jb.ra_part)[(static_cast<size_t>(c) * jb.L + l) * n_ra + i];
+        for (int i = 0; i < n_dy; ++i) da += gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+      }
+      gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.L + l] = da;
+    }
+  }
 }
 
 // one unit per job
@@ -1041,13 +1161,23 @@ __global__ void k_loss_total(Launch la, float scale) {
   const JobDev& jb = *r.jb;
   if (threadIdx.x != 0) return;
   if (*gmem(jb.status)) {
-    *gmem(jb.loss) = __int_as_float(0x7fc00000);
+    if (jb.loss) *gmem(jb.loss) = __int_as_float(0x7fc00000);
     return;
   }
-  double s = 0.0;
-  const PTYCHO_GLOBAL double* lk = gmem(jb.loss_k);
-  for (int k = 0; k < jb.K; ++k) s += lk[k];
-  *gmem(jb.loss) = static_cast<float>(s * scale);
+  if (jb.loss) {
+    double s = 0.0;
+    const PTYCHO_GLOBAL double* lk = gmem(jb.loss_k);
+    for (int k = 0; k < jb.K; ++k) s += lk[k];
+    *gmem(jb.loss) = static_cast<float>(s * scale);
+  }
+  if (jb.g_ratio) {
+    // dL/d alpha_l: ordered sum over positions (the terms carry the scale)
+    for (int l = 0; l < jb.L; ++l) {
+      double s = 0.0;
+      for (int k = 0; k < jb.K; ++k) s += gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.L + l];
+      gmem(jb.g_ratio)[l] = static_cast<float>(s);
+    }
+  }
 }
 
 // Adam on real coordinates.  Segment l selects the variable (0 object,
@@ -1221,25 +1351,26 @@ hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipS
   });
 }
 
-template <int NN, bool WIDE>
+template <int NN, int VAR>
 void launch_det_inst(dim3 g, const Launch& la, const LossDev& loss, int mode, bool spill,
                      hipStream_t s) {
   switch (mode) {
-    case 0: hipLaunchKernelGGL((k_det<NN, 0, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
-    case 1: hipLaunchKernelGGL((k_det<NN, 1, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
-    case 2: hipLaunchKernelGGL((k_det<NN, 2, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
-    default: hipLaunchKernelGGL((k_det<NN, 3, WIDE>), g, dim3(NT), 0, s, la, loss, spill); break;
+    case 0: hipLaunchKernelGGL((k_det<NN, 0, VAR>), g, dim3(NT), 0, s, la, loss, spill); break;
+    case 1: hipLaunchKernelGGL((k_det<NN, 1, (VAR > 1 ? 1 : VAR)>), g, dim3(NT), 0, s, la, loss, spill); break;
+    case 2: hipLaunchKernelGGL((k_det<NN, 2, VAR>), g, dim3(NT), 0, s, la, loss, spill); break;
+    default: hipLaunchKernelGGL((k_det<NN, 3, (VAR > 1 ? 1 : VAR)>), g, dim3(NT), 0, s, la, loss, spill); break;
   }
 }
 
 hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
-                      bool spill, bool wide, hipStream_t s) {
+                      bool spill, int var, hipStream_t s) {
   if (units <= 0) return hipSuccess;
   return with_N(N, [&](auto nc) {
     constexpr int NN = decltype(nc)::value;
     const dim3 g = grid1(units * (NN / rb_det<NN>()));
-    if (wide) launch_det_inst<NN, true>(g, la, loss, mode, spill, s);
-    else launch_det_inst<NN, false>(g, la, loss, mode, spill, s);
+    if (var == 2) launch_det_inst<NN, 2>(g, la, loss, mode, spill, s);
+    else if (var == 1) launch_det_inst<NN, 1>(g, la, loss, mode, spill, s);
+    else launch_det_inst<NN, 0>(g, la, loss, mode, spill, s);
     return hipGetLastError();
   });
 }
@@ -1259,26 +1390,35 @@ hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream
   return hipGetLastError();
 }
 
+template <int NN, int NL, bool RATIO>
+hipError_t launch_col_adj_inst(dim3 g, const Launch& la, size_t dyn_lds, bool grouped,
+                               hipStream_t s) {
+  if (!grouped) {
+    hipLaunchKernelGGL((k_col_adj<NN, NL, false, RATIO>), g, dim3(CNT), 0, s, la);
+    return hipGetLastError();
+  }
+  if (dyn_lds) {
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_col_adj<NN, NL, true, RATIO>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn_lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_col_adj<NN, NL, true, RATIO>), g, dim3(CNT), dyn_lds, s, la);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
-                          bool grouped, hipStream_t s) {
+                          bool grouped, bool ratio, hipStream_t s) {
   if (units <= 0) return hipSuccess;
   return with_N(N, [&](auto nc) {
     constexpr int NN = decltype(nc)::value;
     return host_pad(nl, [&](auto pc) {
       constexpr int NL = decltype(pc)::value;
       const dim3 g = grid1(units * (NN / col_group<NN>()));
-      if (!grouped) {
-        hipLaunchKernelGGL((k_col_adj<NN, NL, false>), g, dim3(CNT), 0, s, la);
-        return hipGetLastError();
+      if constexpr (NL == czt_nb<NN>()) {
+        if (ratio) return launch_col_adj_inst<NN, NL, true>(g, la, dyn_lds, grouped, s);
       }
-      if (dyn_lds) {
-        const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&k_col_adj<NN, NL, true>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn_lds));
-        if (e != hipSuccess) return e;
-      }
-      hipLaunchKernelGGL((k_col_adj<NN, NL, true>), g, dim3(CNT), dyn_lds, s, la);
-      return hipGetLastError();
+      return launch_col_adj_inst<NN, NL, false>(g, la, dyn_lds, grouped, s);
     }, ColList<NN>{});
   });
 }

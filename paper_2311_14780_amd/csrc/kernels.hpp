@@ -43,10 +43,12 @@ struct JobDev {
   float* g_pos;
   float* g_sigma;
   float* g_background;  // [N][N]
+  float* g_ratio;       // [L] dL/d alpha_l (exact-ratio wavelengths), or null
   float* out;           // forward intensities [K][N][N]
   // workspace of this job for one chunk of C positions
   int* status;
   double* loss_k;       // [K]
+  double* ratio_k;      // [K][L] per-position dL/d alpha_l (g_ratio only)
   float2* ramp;         // [C][2][N]    exp(+2 pi i f delta), y then x
   float2* X;            // [C][L][N][N] row-shifted patch, later G_A
   float2* Y;            // [C][L][M][N][N] column DFT -> Psi -> Z -> probe-gradient terms
@@ -57,6 +59,8 @@ struct JobDev {
   float* dy_part;       // [C][L][N / G]
   float* sg_part;       // [C][L][N / G]
   float* dx_part;       // [C][L][N / RBadj]
+  float* ra_part;       // [C][L][N / RBdet] alpha-derivative terms of the detector rows
+  float* rb_part;       // [C][L][N / G]     alpha-derivative terms of the columns
   float* ibuf;          // [C][N][N] (resampling only) I + B, then R^T g
   float* gbuf;          // [C][N][N] (resampling only) weighted dloss/dI'
   int C;                // positions per chunk (iteration i covers [i C, i C + C))
@@ -70,8 +74,8 @@ struct JobDev {
   // a multi-way branch on l that assigns pointers was compiled into code
   // that left the pointer registers of the later cases unset.
   float* var_flat[kVars];
-  float* grad_flat[kVars];  // may be null
-  long long flat_n[kVars];  // floats in each
+  float* grad_flat[kVars + 1];  // may be null; [kVars] = g_ratio (zeroing only)
+  long long flat_n[kVars + 1];  // floats in each
   // Adam (ptycho_step)
   float* adam_m[kVars];
   float* adam_v[kVars];
@@ -148,17 +152,19 @@ hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t 
 hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s);
 // mode: 0 fused loss + adjoint, 1 forward (I + B to ibuf or out; `spill`
 // keeps Psi for mode 2), 2 adjoint from ibuf (R^T g), 3 loss only.
-// wide: some job of the launch uses the exact-ratio propagator (the
-// instance whose LDS holds rows of length 2N)
+// var: 0 zero-padded DFTs only; 1 some wavelength uses the exact-ratio
+// propagator (LDS rows of length 2N); 2 as 1, and the jobs want dL/d alpha
+// (modes 0 and 2: the adjoint recomputes Psi and the alpha-derivative terms)
 hipError_t launch_det(int N, const Launch& la, long long units, const LossDev& loss, int mode,
-                      bool spill, bool wide, hipStream_t s);
+                      bool spill, int var, hipStream_t s);
 hipError_t launch_resample_loss(int N, const Launch& la, long long units, const LossDev& loss,
                                 bool forward, hipStream_t s);
 hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream_t s);
 // grouped: some job of the launch sums its probe-gradient terms over groups
-// of positions (else the single-position instance runs)
+// of positions (else the single-position instance runs); ratio: the jobs want
+// dL/d alpha (exact-ratio launches only)
 hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
-                          bool grouped, hipStream_t s);
+                          bool grouped, bool ratio, hipStream_t s);
 hipError_t launch_row_adj(int N, const Launch& la, long long units, hipStream_t s);
 
 }  // namespace ptycho

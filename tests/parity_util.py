@@ -52,7 +52,7 @@ def oracle_loss_grad(workers=1, **kw):
     res = dict(outs[0])
     for o in outs[1:]:
         res["loss"] += o["loss"]
-        for key in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
+        for key in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background", "g_ratio"):
             res[key] = res[key] + o[key]
     return res
 
@@ -125,6 +125,8 @@ def gpu_grads(prob, kind=0, eps=1e-6, scale=1.0, chunk=0,
         g["g_sigma"] = torch.zeros(prob.K, device=dev)
     if "background" in want:
         g["g_background"] = torch.zeros(prob.N, prob.N, device=dev)
+    if "ratio" in want:
+        g["g_ratio"] = torch.zeros(prob.L, device=dev)
     ws = B.workspace([prob], 1, chunk)
     B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws, stream=stream)
     torch.cuda.synchronize()
@@ -145,7 +147,7 @@ def gpu_forward(prob, chunk=0):
 
 
 def compare(got, ref, tol_grad=1e-4, tol_loss=1e-5,
-            keys=("g_object", "g_probe", "g_pos", "g_sigma", "g_background")):
+            keys=("g_object", "g_probe", "g_pos", "g_sigma", "g_background", "g_ratio")):
     """Relative L2 errors per output; raises with all of them on failure."""
     errs = {"loss": abs(got["loss"] - ref["loss"]) / max(abs(ref["loss"]), 1e-30)}
     for k in keys:

@@ -110,3 +110,68 @@ def test_exact_ratio_chunking_and_mixed_calls_are_bitwise_invariant():
         for k in ("g_object", "g_probe", "g_pos", "g_background"):
             assert np.array_equal(g[k].cpu().numpy(), ref[k]), k
         assert float(g["loss"].cpu()[0]) == ref["loss"]
+
+
+ALL = ("object", "probe", "pos", "sigma", "background", "ratio")
+
+
+def _check_ratio_grad(case, kinds=(0,), workers=1):
+    prob = U.to_problem(case, DEV)
+    for kind in kinds:
+        got = U.gpu_grads(prob, kind=kind, want=ALL)
+        ref = U.oracle_grads(case, kind=kind, workers=workers)
+        print(f"  {case['w'].name} kind {kind} g_ratio gpu {got['g_ratio']} oracle {ref['g_ratio']}")
+        print("  ", U.compare(got, ref), flush=True)
+        # asking for dL/d alpha recomputes Psi in the adjoint: the other
+        # gradients stay those of the plain call
+        plain = U.gpu_grads(prob, kind=kind)
+        for k in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
+            e = U.rel_l2(got[k], plain[k])
+            assert e <= 1e-6, (k, e)
+        assert abs(got["loss"] - plain["loss"]) <= 1e-7 * abs(plain["loss"])
+
+
+def test_ratio_gradient_three_wavelengths():
+    # exact ratios 77.47 and 70.10 plus the reference wavelength at exactly N
+    w = synth.reduced(synth.get_workload("C1"), L=3, M=2, harmonics=(19, 21, 23),
+                      mode_weights=(0.75, 0.25), K=12, name="C1-dz")
+    case = U.make_case(w, with_sigma=True, with_bg=True, with_mask=True, pads=_ratios(w))
+    _check_ratio_grad(case, kinds=(0, 1))
+
+
+def test_ratio_gradient_mixed_pad_and_ratio_wavelengths():
+    # one zero-padded wavelength (no alpha, g_ratio 0) and one exact-ratio one
+    w = synth.reduced(synth.get_workload("C1"), L=2, M=2, harmonics=(19, 23),
+                      mode_weights=(0.75, 0.25), K=8, name="C1-dzmix")
+    case = U.make_case(w, pads=(80, 64.0), with_sigma=True)
+    got = U.gpu_grads(U.to_problem(case, DEV), want=ALL)
+    assert got["g_ratio"][0] == 0.0
+    _check_ratio_grad(case)
+
+
+def test_ratio_gradient_c2_shapes():
+    w = synth.get_workload("C2")
+    case = U.make_case(w, K=4, pads=_ratios(w), workers=U.default_workers())
+    _check_ratio_grad(case, workers=U.default_workers())
+
+
+def test_ratio_gradient_tilted_plane_resampling():
+    w = synth.get_workload("C5")
+    case = U.make_case(w, K=3, pads=_ratios(w), workers=U.default_workers())
+    _check_ratio_grad(case, workers=U.default_workers())
+
+
+def test_ratio_gradient_n512():
+    w = synth.reduced(synth.get_workload("C3"), K=2, M=2, mode_weights=(0.7, 0.3), name="C3-dz")
+    case = U.make_case(w, pads=_ratios(w), workers=U.default_workers())
+    _check_ratio_grad(case, workers=U.default_workers())
+
+
+def test_ratio_gradient_is_chunk_invariant():
+    w = synth.reduced(synth.get_workload("C1"), L=2, M=2, harmonics=(19, 23),
+                      mode_weights=(0.75, 0.25), K=9, name="C1-dzc")
+    prob = U.to_problem(U.make_case(w, pads=_ratios(w)), DEV)
+    a = U.gpu_grads(prob, want=ALL)
+    b = U.gpu_grads(prob, want=ALL, chunk=4)
+    for k in ("g_ratio", "g_object", "g_probe", "g_pos", "g_background"):
+        assert np.array_equal(a[k], b[k]), k
