@@ -22,12 +22,13 @@ identities of the gradient and central finite differences.
 from .model import (
     split_positions, shift_patch, shift_patch_adjoint, propagate,
     propagate_adjoint, is_ratio, scaled_dft_matrix, propagate_dalpha, resample, resample_adjoint,
-    forward, loss_grad, pointwise_loss, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN, LOSS_VJP,
+    forward, loss_grad, pointwise_loss, regulariser, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN,
+    LOSS_VJP, LOSS_MIXED,
 )
 
 __all__ = [
     "split_positions", "shift_patch", "shift_patch_adjoint", "propagate",
     "propagate_adjoint", "is_ratio", "scaled_dft_matrix", "propagate_dalpha", "resample",
     "resample_adjoint", "forward", "loss_grad", "pointwise_loss", "LOSS_AMPLITUDE", "LOSS_POISSON",
-    "LOSS_GAUSSIAN", "LOSS_VJP",
+    "LOSS_GAUSSIAN", "LOSS_VJP", "LOSS_MIXED", "regulariser",
 ]

@@ -36,7 +36,15 @@ design notes):
   amplitude (MSE on the modulus): (sqrt(I'+eps) - sqrt(Î+eps))^2;
   Poisson: (I'+eps) - (Î+eps) ln(I'+eps);
   Gaussian: (I' - Î)^2;
-  VJP: u * I' with u = ``measured`` an upstream gradient (mask ignored).
+  VJP: u * I' with u = ``measured`` an upstream gradient (mask ignored);
+  mixed Poisson-Gaussian noise (the paper's MLE with mixed noise
+  statistics), Gaussian approximation with variance I' + v (v the read-noise
+  variance): (I' - Î)^2 / (I' + v) + ln(I' + v).
+* Regularisers on the object amplitude a = |O| (the paper applies L1 and TV
+  to the amplitude): R = l1 sum a + tv sum sqrt(dy^2 + dx^2 + delta^2), with
+  forward differences dy = a[y+1, x] - a[y, x], dx = a[y, x+1] - a[y, x]
+  (zero past the last row / column), summed over every wavelength and sample
+  mode; R is added to the loss unscaled.
 * Gradients use the convention G = dL/dRe + i dL/dIm.
 """
 from __future__ import annotations
@@ -47,6 +55,7 @@ LOSS_AMPLITUDE = 0
 LOSS_POISSON = 1
 LOSS_GAUSSIAN = 2
 LOSS_VJP = 3
+LOSS_MIXED = 4
 
 
 # ----------------------------------------------------------------- f2: shift
@@ -162,10 +171,14 @@ def resample_adjoint(g: np.ndarray, idx: np.ndarray, w: np.ndarray) -> np.ndarra
     return out.reshape(N, N)
 
 
-def pointwise_loss(I: np.ndarray, meas: np.ndarray, kind: int, eps: float):
+def pointwise_loss(I: np.ndarray, meas: np.ndarray, kind: int, eps: float, noise_var: float = 1.0):
     """Per-pixel loss and its derivative with respect to the prediction I."""
     I = np.asarray(I, np.float64)
     meas = np.asarray(meas, np.float64)
+    if kind == LOSS_MIXED:
+        q = I + noise_var
+        d = I - meas
+        return d * d / q + np.log(q), 2.0 * d / q - (d / q) ** 2 + 1.0 / q
     if kind == LOSS_AMPLITUDE:
         a = np.sqrt(I + eps)
         b = np.sqrt(meas + eps)
@@ -177,6 +190,26 @@ def pointwise_loss(I: np.ndarray, meas: np.ndarray, kind: int, eps: float):
     if kind == LOSS_VJP:
         return meas * I, meas.copy()
     raise ValueError(f"unknown loss kind {kind}")
+
+
+# ------------------------------------------------------------ regularisers
+def regulariser(obj, l1: float, tv: float, tv_eps: float):
+    """Value and gradient (G = dR/dRe + i dR/dIm) of the amplitude L1 and
+    smoothed isotropic TV terms, for an object [..., H, W]."""
+    O = np.asarray(obj, np.complex128)
+    a = np.abs(O)
+    dy = np.zeros_like(a)
+    dx = np.zeros_like(a)
+    dy[..., :-1, :] = a[..., 1:, :] - a[..., :-1, :]
+    dx[..., :, :-1] = a[..., :, 1:] - a[..., :, :-1]
+    t = np.sqrt(dy * dy + dx * dx + tv_eps * tv_eps)
+    value = l1 * float(np.sum(a)) + tv * float(np.sum(t))
+    # dR/da: own term -(dy + dx)/t, plus the terms of the pixels above and left
+    ga = np.full_like(a, l1) - tv * (dy + dx) / t
+    ga[..., 1:, :] += tv * (dy / t)[..., :-1, :]
+    ga[..., :, 1:] += tv * (dx / t)[..., :, :-1]
+    phase = np.where(a > 0, O / np.where(a > 0, a, 1.0), 0.0)
+    return value, ga * phase
 
 
 # ------------------------------------------------------------- shape helpers
@@ -239,11 +272,14 @@ def forward(obj, probe, pos, pads, sigma=None, background=None, resample_table=N
 
 def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
               scale=1.0, sigma=None, background=None, mask=None,
-              resample_table=None, positions=None):
+              resample_table=None, positions=None, noise_var=1.0, l1=0.0, tv=0.0,
+              tv_eps=1e-3):
     """Loss and gradients w.r.t. object, probe, positions and sigma.
 
     ``positions`` restricts the sums over k to a subset (the loss is a sum of
-    per-position terms, so the full gradient is the sum over a partition).
+    per-position terms, so the full gradient is the sum over a partition);
+    the regulariser (l1, tv) belongs to no position and is added only when
+    ``positions`` is None.
     Returns a dict: loss (float), g_object (shape of ``obj``), g_probe
     [L][M][N][N], g_pos [K][2], g_sigma [K] (zero outside the subset),
     g_background [N][N] (the background enters f5 before the resampling, so
@@ -277,7 +313,7 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
         if background is not None:
             I = I + np.asarray(background, np.float64)
         Ip = resample(I, *resample_table) if resample_table is not None else I
-        ell, dell = pointwise_loss(Ip, measured[k], kind, eps)
+        ell, dell = pointwise_loss(Ip, measured[k], kind, eps, noise_var)
         total += float(np.sum(w * ell))
         # dL/dI, pulled back through the resampling
         g = w * dell
@@ -312,6 +348,11 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     g_sig *= scale
     g_bg *= scale
     g_ratio *= scale
-    return dict(loss=total * scale, g_object=g_obj[:, 0] if squeeze else g_obj,
+    total *= scale
+    if (l1 or tv) and positions is None:
+        rv, rg = regulariser(obj, l1, tv, tv_eps)
+        total += rv
+        g_obj += rg
+    return dict(loss=total, g_object=g_obj[:, 0] if squeeze else g_obj,
                 g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig, g_background=g_bg,
                 g_ratio=g_ratio)

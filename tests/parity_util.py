@@ -54,6 +54,11 @@ def oracle_loss_grad(workers=1, **kw):
         res["loss"] += o["loss"]
         for key in ("g_object", "g_probe", "g_pos", "g_sigma", "g_background", "g_ratio"):
             res[key] = res[key] + o[key]
+    if kw.get("l1") or kw.get("tv"):  # the regulariser belongs to no position
+        rv, rg = oracle.regulariser(kw["obj"], kw.get("l1", 0.0), kw.get("tv", 0.0),
+                                    kw.get("tv_eps", 1e-3))
+        res["loss"] += rv
+        res["g_object"] = res["g_object"] + rg
     return res
 
 
@@ -83,18 +88,20 @@ def make_case(w, K=None, with_sigma=False, with_bg=False, with_mask=False, seed_
                        sigma=sigma, bg=bg, table=table, workers=workers)
     meas = synth.sample_counts(I, w.seed + seed_offset)
     # the model and the GPU both consume the float32 / complex64 inputs
-    obj = start["object"][:, 0].astype(np.complex64)
+    obj = start["object"]  # [L][Ns][H][W]; one sample mode is passed as [L][H][W]
+    obj = (obj[:, 0] if obj.shape[1] == 1 else obj).astype(np.complex64)
     prb = start["probe"].astype(np.complex64)
     return dict(w=w, obj=obj, prb=prb, pos=start["pos"].copy(), pads=tuple(truth["pads"]),
                 meas=meas, sigma=sigma, bg=bg, mask=mask, table=table, truth=truth)
 
 
-def oracle_grads(case, kind=0, eps=1e-6, scale=1.0, workers=1):
+def oracle_grads(case, kind=0, eps=1e-6, scale=1.0, workers=1, **extra):
+    """``extra``: noise_var, l1, tv, tv_eps of oracle.loss_grad."""
     return oracle_loss_grad(
         workers=workers, obj=case["obj"].astype(np.complex128), probe=case["prb"].astype(np.complex128),
         pos=case["pos"], pads=case["pads"], measured=case["meas"], kind=kind, eps=eps,
         scale=scale, sigma=case["sigma"], background=case["bg"], mask=case["mask"],
-        resample_table=case["table"])
+        resample_table=case["table"], **extra)
 
 
 def to_problem(case, device):
@@ -153,7 +160,7 @@ def compare(got, ref, tol_grad=1e-4, tol_loss=1e-5,
     for k in keys:
         if k in got:
             r = ref[k]
-            if k == "g_object" and r.ndim == 4:
+            if k == "g_object" and r.ndim == 4 and np.asarray(got[k]).ndim == 3:
                 r = r[:, 0]
             errs[k] = rel_l2(got[k], r)
     bad = {k: v for k, v in errs.items() if v > (tol_loss if k == "loss" else tol_grad)}
