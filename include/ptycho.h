@@ -66,6 +66,7 @@ extern "C" {
 
 #define PTYCHO_MAX_WAVELENGTHS 8
 #define PTYCHO_MAX_MODES 16
+#define PTYCHO_MAX_SAMPLE_MODES 16  /* and L * Ns <= 16 */
 
 enum {
   PTYCHO_OK = 0,
@@ -99,7 +100,7 @@ typedef struct ptycho_job {
                                            exact-ratio propagator, or 0 (zero-padded DFT
                                            of size pad[l]); negative, NaN or infinite:
                                            PTYCHO_EINVAL; 0 < alpha < N: PTYCHO_ERANGE */
-  float* object;            /* complex64 [L][H][W]   O_l; written only by ptycho_step */
+  float* object;            /* complex64 [L][Ns][H][W] O_{l,n}; written only by ptycho_step */
   float* probe;             /* complex64 [L][M][N][N] P_{l,m}; written only by ptycho_step */
   float* pos;               /* float32 [K][2]        s_k = (y, x); written only by ptycho_step */
   float* sigma;             /* float32 [K] power coefficients sigma_k, or NULL (= 1);
@@ -119,6 +120,10 @@ typedef struct ptycho_job {
   const int32_t* rsT_col;
   const float* rsT_val;
   const float* measured;    /* float32 [K][N][N] measured Î_k, or upstream dL/dI' (VJP) */
+  int32_t Ns;               /* sample modes O_{l,n} of Eq. 1 (0 or 1: one).  With Ns > 1
+                               the object is complex64 [L][Ns][H][W], every (l, n) pair is
+                               propagated with every probe mode P_{l,m} and summed
+                               incoherently; L * Ns <= 16 */
 } ptycho_job_t;
 
 typedef struct ptycho_loss {
@@ -131,7 +136,7 @@ typedef struct ptycho_loss {
    (a NULL gradient also skips the work that only it needs). */
 typedef struct ptycho_grads {
   float* loss;          /* float32 [1] */
-  float* g_object;      /* complex64 [L][H][W] */
+  float* g_object;      /* complex64 [L][Ns][H][W] */
   float* g_probe;       /* complex64 [L][M][N][N] */
   float* g_pos;         /* float32 [K][2] */
   float* g_sigma;       /* float32 [K] */

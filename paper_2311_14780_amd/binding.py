@@ -43,7 +43,8 @@ class JobT(ctypes.Structure):
                 ("ratio", ctypes.c_double * MAX_WAVELENGTHS),
                 ("object", _c_p), ("probe", _c_p), ("pos", _c_p), ("sigma", _c_p),
                 ("background", _c_p), ("mask", _c_p), ("rs_idx", _c_p), ("rs_w", _c_p),
-                ("rsT_ptr", _c_p), ("rsT_col", _c_p), ("rsT_val", _c_p), ("measured", _c_p)]
+                ("rsT_ptr", _c_p), ("rsT_col", _c_p), ("rsT_val", _c_p), ("measured", _c_p),
+                ("Ns", _c_i32)]
 
 
 class LossT(ctypes.Structure):
@@ -138,7 +139,8 @@ def _stream(stream) -> ctypes.c_void_p:
 class Problem:
     """Device tensors of one reconstruction job (the variables of Eq. 1).
 
-    object complex64 [L][H][W]; probe complex64 [L][M][N][N]; pos float32
+    object complex64 [L][H][W] or [L][Ns][H][W] (Ns sample modes);
+    probe complex64 [L][M][N][N]; pos float32
     [K][2]; pads: per wavelength, an int (zero-padded DFT size) or a float
     (exact sampling ratio alpha of the exact-ratio propagator); measured
     float32 [K][N][N];
@@ -172,10 +174,15 @@ class Problem:
     def N(self):
         return int(self.probe.shape[-1])
 
+    @property
+    def Ns(self):
+        return int(self.object.shape[1]) if self.object.dim() == 4 else 1
+
     def to_job(self) -> JobT:
         j = JobT()
         j.K, j.L, j.M, j.N = self.K, self.L, self.M, self.N
         j.H, j.W = int(self.object.shape[-2]), int(self.object.shape[-1])
+        j.Ns = self.Ns
         if len(self.pads) != self.L:
             raise ValueError("one pad per wavelength is required")
         _set_pads(j, self.pads)

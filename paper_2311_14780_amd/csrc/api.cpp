@@ -177,9 +177,11 @@ bool has_resample(const ptycho_job_t& j) { return j.rs_idx != nullptr; }
 
 // check_ptrs = false: only sizes are validated (workspace queries).
 int validate_job(const ptycho_job_t& j, bool need_measured, bool check_ptrs = true) {
+  if (j.Ns < 0 || j.Ns > PTYCHO_MAX_SAMPLE_MODES) return PTYCHO_EINVAL;
   if (j.K < 0 || j.L < 1 || j.L > PTYCHO_MAX_WAVELENGTHS || j.M < 1 || j.M > PTYCHO_MAX_MODES ||
       j.N < 1 || j.H < 1 || j.W < 1)
     return PTYCHO_EINVAL;
+  if (j.L * std::max(j.Ns, 1) > kMaxL) return PTYCHO_EINVAL;  // slots
   if (j.H < j.N || j.W < j.N) return PTYCHO_ERANGE;
   if (static_cast<long long>(j.H) * j.W >= (1LL << 31)) return PTYCHO_EINVAL;
   bool n_ok = false;
@@ -206,6 +208,10 @@ int validate_job(const ptycho_job_t& j, bool need_measured, bool check_ptrs = tr
   return PTYCHO_OK;
 }
 
+// Sample modes (0 means one) and slots s = l Ns + n (wavelength, sample mode).
+int ns_of(const ptycho_job_t& j) { return j.Ns > 1 ? j.Ns : 1; }
+int slots_of(const ptycho_job_t& j) { return j.L * ns_of(j); }
+
 bool is_czt(const ptycho_job_t& j, int l) { return j.ratio[l] != 0.0; }
 
 bool any_czt(const ptycho_job_t& j) {
@@ -217,6 +223,7 @@ bool any_czt(const ptycho_job_t& j) {
 // DFT length the kernels run for wavelength l: the pad, or the Bluestein
 // length of the exact-ratio propagator.
 int eff_pad(const ptycho_job_t& j, int l) { return is_czt(j, l) ? czt_len(j.N) : j.pad[l]; }
+int eff_pad_slot(const ptycho_job_t& j, int s) { return eff_pad(j, s / ns_of(j)); }
 
 // Chirp tables of a job's exact-ratio wavelengths (one region per wavelength).
 size_t czt_table_bytes(const ptycho_job_t& j) {
@@ -236,7 +243,7 @@ int n_loss_of(const ptycho_job_t& j) {
 
 // Bytes of workspace that scale with the number of positions in a chunk.
 size_t per_position_bytes(const ptycho_job_t& j, int which) {
-  const size_t N = j.N, L = j.L, M = j.M;
+  const size_t N = j.N, L = slots_of(j), M = j.M;
   const size_t plane = N * N;
   size_t b = 0;
   b += align_up(2 * N * sizeof(float2));          // ramp
@@ -343,7 +350,7 @@ bool wants_ratio(const Call& c, int i) {
 // Floats of variable v (0 object, 1 probe, 2 positions, 3 sigma, 4 background).
 size_t var_floats(const ptycho_job_t& j, int v) {
   switch (v) {
-    case 0: return 2ull * j.L * j.H * j.W;
+    case 0: return 2ull * slots_of(j) * j.H * j.W;
     case 1: return 2ull * j.L * j.M * j.N * j.N;
     case 2: return 2ull * j.K;
     case 3: return static_cast<size_t>(j.K);
@@ -450,21 +457,25 @@ void fill_job(Call& c, int i, char** cursor) {
   d.rsT_val = j.rsT_val;
   d.measured = j.measured;
   d.K = j.K;
-  d.L = j.L;
+  d.L = slots_of(j);
+  d.Lw = j.L;
+  d.Ns = ns_of(j);
   d.M = j.M;
   d.N = j.N;
   d.H = j.H;
   d.W = j.W;
   d.tw_N = twiddles(j.N);
-  for (int l = 0; l < kMaxL; ++l) {
-    const int nl = l < j.L ? eff_pad(j, l) : j.N;
-    d.pad[l] = nl;
-    d.pad_scale[l] = static_cast<float>(1.0 / std::sqrt(static_cast<double>(nl)));
-    d.tw_pad[l] = twiddles(nl);
-    if (l < j.L && is_czt(j, l)) {
-      d.czt[l] = reinterpret_cast<float2*>(c.czt_tab[i] + l * align_up(4 * static_cast<size_t>(j.N) *
-                                                                        sizeof(float2)));
-      d.czt_alpha[l] = j.ratio[l];
+  for (int sl = 0; sl < kMaxL; ++sl) {  // per slot, from its wavelength w
+    const bool used = sl < slots_of(j);
+    const int w = sl / ns_of(j);
+    const int nl = used ? eff_pad(j, w) : j.N;
+    d.pad[sl] = nl;
+    d.pad_scale[sl] = static_cast<float>(1.0 / std::sqrt(static_cast<double>(nl)));
+    d.tw_pad[sl] = twiddles(nl);
+    if (used && is_czt(j, w)) {
+      d.czt[sl] = reinterpret_cast<float2*>(c.czt_tab[i] + w * align_up(4 * static_cast<size_t>(j.N) *
+                                                                         sizeof(float2)));
+      d.czt_alpha[sl] = j.ratio[w];
     }
   }
   if (c.grads) {
@@ -495,7 +506,7 @@ void fill_job(Call& c, int i, char** cursor) {
   d.status = c.status + i;
   d.loss_k = c.loss_k[i];
   const int C = c.chunk[i];
-  const size_t N = j.N, L = j.L, M = j.M, plane = N * N;
+  const size_t N = j.N, L = slots_of(j), M = j.M, plane = N * N;
   auto take = [&](size_t bytes) {
     char* r = *cursor;
     *cursor += align_up(bytes);
@@ -598,8 +609,8 @@ int run_prologue(Call& c, hipStream_t s) {
   for (int i = 0; i < c.n; ++i) ph.add(val, i, 0, (c.jobs[i].K + 255) / 256);
   auto czt = ph.begin();
   for (int i = 0; i < c.n; ++i)
-    for (int l = 0; l < c.jobs[i].L; ++l)
-      if (is_czt(c.jobs[i], l)) ph.add(czt, i, l, czt_table_blocks(c.jobs[i].N));
+    for (int l = 0; l < c.jobs[i].L; ++l)  // one table per wavelength, at its first slot
+      if (is_czt(c.jobs[i], l)) ph.add(czt, i, l * ns_of(c.jobs[i]), czt_table_blocks(c.jobs[i].N));
   int e = upload_phase(c, ph, s);
   if (e) return e;
   LAUNCH(KC_FILL, launch_simple(KZeroGrads, launch_of(c, zero, 0), zero.units, s));
@@ -626,7 +637,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
   for (size_t q = 0; q < members.size(); ++q) ph.add(prep, members[q], 0, cnt[q]);
   auto rowf = ph.begin();
   for (size_t q = 0; q < members.size(); ++q)
-    for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowf, members[q], l, cnt[q]);
+    for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l) ph.add(rowf, members[q], l, cnt[q]);
   // distinct DFT sizes of the group, in first-seen order
   std::vector<int> nls;
   const int var = key.ratio_grad ? 2 : (key.wide ? 1 : 0);
@@ -635,12 +646,13 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
       if (std::find(nls.begin(), nls.end(), eff_pad(c.jobs[i], l)) == nls.end())
         nls.push_back(eff_pad(c.jobs[i], l));
   }
+  // work units below run over slots (wavelength x sample mode)
   std::vector<Phase::Item> colf(nls.size()), cola(nls.size());
   for (size_t p = 0; p < nls.size(); ++p) {
     colf[p] = ph.begin();
     for (size_t q = 0; q < members.size(); ++q)
-      for (int l = 0; l < c.jobs[members[q]].L; ++l)
-        if (eff_pad(c.jobs[members[q]], l) == nls[p]) ph.add(colf[p], members[q], l, cnt[q]);
+      for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l)
+        if (eff_pad_slot(c.jobs[members[q]], l) == nls[p]) ph.add(colf[p], members[q], l, cnt[q]);
   }
   auto det = ph.begin();
   for (size_t q = 0; q < members.size(); ++q) ph.add(det, members[q], 0, cnt[q]);
@@ -650,8 +662,9 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
       cola[p] = ph.begin();
       for (size_t q = 0; q < members.size(); ++q) {
         const int pg = c.pgroup[members[q]];
-        for (int l = 0; l < c.jobs[members[q]].L; ++l)
-          if (eff_pad(c.jobs[members[q]], l) == nls[p]) ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
+        for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l)
+          if (eff_pad_slot(c.jobs[members[q]], l) == nls[p])
+            ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
       }
     }
     prob = ph.begin();
@@ -664,14 +677,14 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     for (size_t q = 0; q < members.size(); ++q) {
       const ptycho_grads_t& g = c.grads[members[q]];
       if (!(g.g_object || g.g_pos)) continue;
-      for (int l = 0; l < c.jobs[members[q]].L; ++l) ph.add(rowa, members[q], l, cnt[q]);
+      for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l) ph.add(rowa, members[q], l, cnt[q]);
     }
     obj = ph.begin();
     for (size_t q = 0; q < members.size(); ++q) {
       const ptycho_job_t& j = c.jobs[members[q]];
       if (!cnt[q] || !c.grads[members[q]].g_object) continue;
       const long long tiles = static_cast<long long>((j.W + 63) / 64) * ((j.H + 15) / 16);
-      for (int l = 0; l < j.L; ++l) ph.add(obj, members[q], l, tiles);
+      for (int l = 0; l < slots_of(j); ++l) ph.add(obj, members[q], l, tiles);
     }
   }
   auto bgr = ph.begin();

@@ -350,7 +350,8 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
   __syncthreads();
   const float ps = jb.pad_scale[l];
   for (int m = 0; m < jb.M; ++m) {
-    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
+    const gf2* __restrict__ P =
+        gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * N * N + x0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * CNT, line = e % G, i = e / G;
@@ -822,7 +823,8 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   if constexpr (!GROUPED) zload(0, zcur);
   for (int m = 0; m < jb.M; ++m) {
     gf2* __restrict__ Z = Z0 + static_cast<size_t>(m) * N * N;
-    const gf2* __restrict__ P = gmem(jb.probe) + (static_cast<size_t>(l) * jb.M + m) * N * N + x0;
+    const gf2* __restrict__ P =
+        gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * N * N + x0;
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
     };
@@ -942,8 +944,9 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
 }
 
 // ------------------------------------------- probe gradient: ordered k sum
-// g_probe[l][m][pix] += sum over groups, ascending, of Y[first c of group][l][m][pix]
-// units: (l, m * nblk + pixel block), nblk = ceil(N^2 / NT)
+// g_probe[l][m][pix] += sum over position groups (ascending) and sample
+// modes n (ascending) of Y[first c of group][l Ns + n][m][pix]
+// units: (wavelength l, m * nblk + pixel block), nblk = ceil(N^2 / NT)
 __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
@@ -954,13 +957,16 @@ __global__ __launch_bounds__(NT) void k_probe_reduce(Launch la) {
   const size_t pix = static_cast<size_t>(blk) * NT + threadIdx.x;
   if (pix >= plane) return;
   const int lm = r.l * jb.M + m;
-  const size_t stride = static_cast<size_t>(jb.L) * jb.M * plane;
-  const gf2* __restrict__ src = gmem(jb.Y) + static_cast<size_t>(lm) * plane + pix;
+  const size_t stride = static_cast<size_t>(jb.L) * jb.M * plane;  // one position
+  const size_t nstride = static_cast<size_t>(jb.M) * plane;         // one sample mode
+  const gf2* __restrict__ src =
+      gmem(jb.Y) + (static_cast<size_t>(r.l) * jb.Ns * jb.M + m) * plane + pix;
   gf2* __restrict__ gp = gmem(jb.g_probe);
   float2 acc = ldv(gp, static_cast<size_t>(lm) * plane + pix);
   const int C = min(jb.C, jb.K - la.iter * jb.C);
   const int PG = jb.probe_group;  // one summed term per group of positions
-  for (int c = 0; c < C; c += PG) acc = cadd(acc, ldv(src, c * stride));
+  for (int c = 0; c < C; c += PG)
+    for (int n = 0; n < jb.Ns; ++n) acc = cadd(acc, ldv(src, c * stride + n * nstride));
   stv(gp, static_cast<size_t>(lm) * plane + pix, acc);
 }
 
@@ -1144,13 +1150,14 @@ __global__ void k_finalize_chunk(Launch la) {
   if (jb.g_sigma) gmem(jb.g_sigma)[k] = gs;
   if (jb.g_ratio) {
     const int n_ra = jb.N / rb_det_dev(jb.N);
-    for (int l = 0; l < jb.L; ++l) {
+    for (int w = 0; w < jb.Lw; ++w) {
       double da = 0.0;
-      if (jb.czt[l]) {
+      for (int l = w * jb.Ns; l < (w + 1) * jb.Ns; ++l) {  // slots of wavelength w
+        if (!jb.czt[l]) continue;
         for (int i = 0; i < n_ra; ++i) da += gmem(jb.ra_part)[(static_cast<size_t>(c) * jb.L + l) * n_ra + i];
         for (int i = 0; i < n_dy; ++i) da += gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
       }
-      gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.L + l] = da;
+      gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.Lw + w] = da;
     }
   }
 }
@@ -1172,10 +1179,10 @@ __global__ void k_loss_total(Launch la, float scale) {
   }
   if (jb.g_ratio) {
     // dL/d alpha_l: ordered sum over positions (the terms carry the scale)
-    for (int l = 0; l < jb.L; ++l) {
+    for (int w = 0; w < jb.Lw; ++w) {
       double s = 0.0;
-      for (int k = 0; k < jb.K; ++k) s += gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.L + l];
-      gmem(jb.g_ratio)[l] = static_cast<float>(s);
+      for (int k = 0; k < jb.K; ++k) s += gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.Lw + w];
+      gmem(jb.g_ratio)[w] = static_cast<float>(s);
     }
   }
 }

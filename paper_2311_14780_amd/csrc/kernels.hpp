@@ -7,7 +7,7 @@
 
 namespace ptycho {
 
-constexpr int kMaxL = 8;
+constexpr int kMaxL = 16;  // slots: wavelength x sample mode
 constexpr int kVars = 5;  // object, probe, positions, sigma, background
 
 // One job of a call, as seen by the kernels (kept in device memory; every
@@ -26,7 +26,12 @@ struct JobDev {
   const int32_t* rsT_col;
   const float* rsT_val;
   const float* measured;  // [K][N][N]
+  // L counts slots s = l Ns + n (wavelength l, sample mode n): the object,
+  // every per-wavelength workspace array and the per-slot tables below are
+  // indexed by slot; the probe of slot s is P_{s / Ns} (Eq. 1's sample modes
+  // share the illumination).
   int K, L, M, N, H, W;
+  int Lw, Ns;              // wavelengths, sample modes (L = Lw Ns)
   int pad[kMaxL];          // DFT length per wavelength (2N for the exact-ratio propagator)
   float pad_scale[kMaxL];  // 1 / sqrt(pad[l]) (zero-padded DFT only)
   const float2* tw_N;            // twiddles of length N
@@ -48,7 +53,7 @@ struct JobDev {
   // workspace of this job for one chunk of C positions
   int* status;
   double* loss_k;       // [K]
-  double* ratio_k;      // [K][L] per-position dL/d alpha_l (g_ratio only)
+  double* ratio_k;      // [K][Lw] per-position dL/d alpha_l (g_ratio only)
   float2* ramp;         // [C][2][N]    exp(+2 pi i f delta), y then x
   float2* X;            // [C][L][N][N] row-shifted patch, later G_A
   float2* Y;            // [C][L][M][N][N] column DFT -> Psi -> Z -> probe-gradient terms

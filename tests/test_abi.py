@@ -222,3 +222,20 @@ def test_adam_of_sigma_needs_its_state():
     rc = B.lib().ptycho_step(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
                              ctypes.byref(adam), ctypes.c_void_p(0x2000), 1 << 20, None)
     assert rc == B.PTYCHO_EINVAL
+
+
+@pytest.mark.parametrize("L,Ns,code", [(2, -1, B.PTYCHO_EINVAL), (2, 17, B.PTYCHO_EINVAL),
+                                       (8, 3, B.PTYCHO_EINVAL), (8, 2, 0), (2, 0, 0)])
+def test_sample_mode_limits(L, Ns, code):
+    j = _job(L=L, pads=(64,) * L)
+    j.Ns = Ns
+    assert _ws_bytes(j)[0] == code
+
+
+def test_sample_modes_scale_the_per_position_workspace():
+    j1, j2 = _job(K=8), _job(K=8)
+    j2.Ns = 3
+    b1 = _ws_bytes(j1, chunk=4)[1]
+    b2 = _ws_bytes(j2, chunk=4)[1]
+    # X, GX and Y grow with the slot count (L Ns)
+    assert b2 - b1 >= 4 * 8 * 64 * 64 * 2 * (2 + 3)
