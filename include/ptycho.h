@@ -82,8 +82,12 @@ enum {
   PTYCHO_LOSS_AMPLITUDE = 0, /* sum w (sqrt(I'+eps) - sqrt(Î+eps))^2, MSE on the modulus */
   PTYCHO_LOSS_POISSON = 1,   /* sum w ((I'+eps) - (Î+eps) ln(I'+eps)), Poisson NLL */
   PTYCHO_LOSS_GAUSSIAN = 2,  /* sum w (I' - Î)^2, Gaussian NLL with unit variance */
-  PTYCHO_LOSS_VJP = 3        /* sum u I' with u = `measured`: vector-Jacobian product of
+  PTYCHO_LOSS_VJP = 3,       /* sum u I' with u = `measured`: vector-Jacobian product of
                                 the forward model (mask ignored) */
+  PTYCHO_LOSS_MIXED = 4      /* sum w ((I' - Î)^2 / (I' + v) + ln(I' + v)): MLE with mixed
+                                Poisson-Gaussian noise statistics (same section), Gaussian
+                                approximation with variance I' + v, v = noise_var (the read-
+                                noise variance in photons^2, > 0) */
 };
 
 /* One reconstruction job: the variables and fixed inputs of Eq. 1. */
@@ -127,9 +131,16 @@ typedef struct ptycho_job {
 } ptycho_job_t;
 
 typedef struct ptycho_loss {
-  int32_t kind;  /* PTYCHO_LOSS_* */
-  float eps;     /* added inside sqrt / log (photons); e.g. 1e-6 */
-  float scale;   /* loss and every gradient are multiplied by scale (e.g. 1/K) */
+  int32_t kind;     /* PTYCHO_LOSS_* */
+  float eps;        /* added inside sqrt / log (photons); e.g. 1e-6 */
+  float scale;      /* the data term and its gradients are multiplied by scale (e.g. 1/K) */
+  float noise_var;  /* PTYCHO_LOSS_MIXED: read-noise variance v > 0 */
+  /* Regularisation of the object amplitude a = |O| (the paper's L1 and TV
+     regularisations, applied to the amplitude), added to the loss unscaled:
+     l1 sum a + tv sum sqrt(dy^2 + dx^2 + tv_eps^2), dy, dx forward differences
+     of a within each (wavelength, sample mode) plane, zero past the last
+     row / column.  Zero weights switch a term off (and cost nothing). */
+  float l1, tv, tv_eps;
 } ptycho_loss_t;
 
 /* Outputs, one per job.  Every pointer may be NULL to skip that output

@@ -32,6 +32,7 @@ LOSS_AMPLITUDE = 0
 LOSS_POISSON = 1
 LOSS_GAUSSIAN = 2
 LOSS_VJP = 3
+LOSS_MIXED = 4
 
 _c_i32 = ctypes.c_int32
 _c_p = ctypes.c_void_p
@@ -48,7 +49,14 @@ class JobT(ctypes.Structure):
 
 
 class LossT(ctypes.Structure):
-    _fields_ = [("kind", _c_i32), ("eps", ctypes.c_float), ("scale", ctypes.c_float)]
+    _fields_ = [("kind", _c_i32), ("eps", ctypes.c_float), ("scale", ctypes.c_float),
+                ("noise_var", ctypes.c_float), ("l1", ctypes.c_float), ("tv", ctypes.c_float),
+                ("tv_eps", ctypes.c_float)]
+
+
+def _loss(kind, eps, scale, noise_var=1.0, l1=0.0, tv=0.0, tv_eps=1e-3) -> LossT:
+    return LossT(int(kind), float(eps), float(scale), float(noise_var), float(l1), float(tv),
+                 float(tv_eps))
 
 
 class GradsT(ctypes.Structure):
@@ -267,8 +275,9 @@ def _grads_array(grads: Sequence[dict]):
 
 def ptycho_loss_grad(problems: Sequence[Problem], grads: Sequence[dict], kind: int = 0,
                      eps: float = 1e-6, scale: float = 1.0, workspace: torch.Tensor = None,
-                     stream=None) -> None:
-    loss = LossT(int(kind), float(eps), float(scale))
+                     stream=None, **reg) -> None:
+    """``reg``: noise_var (mixed-noise loss), l1, tv, tv_eps (regularisers)."""
+    loss = _loss(kind, eps, scale, **reg)
     code = lib().ptycho_loss_grad(_jobs(problems), len(problems), ctypes.byref(loss),
                                   _grads_array(grads), _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), _stream(stream))
@@ -278,8 +287,8 @@ def ptycho_loss_grad(problems: Sequence[Problem], grads: Sequence[dict], kind: i
 
 def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequence[dict],
                 kind: int = 0, eps: float = 1e-6, scale: float = 1.0,
-                workspace: torch.Tensor = None, stream=None) -> None:
-    loss = LossT(int(kind), float(eps), float(scale))
+                workspace: torch.Tensor = None, stream=None, **reg) -> None:
+    loss = _loss(kind, eps, scale, **reg)
     arr = (AdamT * len(adam))()
     for i, a in enumerate(adam):
         arr[i].m_object, arr[i].v_object = _ptr(a.get("m_object")), _ptr(a.get("v_object"))

@@ -236,6 +236,14 @@ size_t ratio_k_bytes(const ptycho_job_t& j) {
   return any_czt(j) ? align_up(std::max<size_t>(j.K, 1) * j.L * sizeof(double)) : 0;
 }
 
+// Regulariser values per pixel block of every slot of the object.
+size_t reg_blocks(const ptycho_job_t& j) {
+  return (static_cast<size_t>(j.H) * j.W + kRegBlock - 1) / kRegBlock;
+}
+size_t reg_bytes(const ptycho_job_t& j) {
+  return align_up(static_cast<size_t>(slots_of(j)) * reg_blocks(j) * sizeof(float));
+}
+
 int n_loss_of(const ptycho_job_t& j) {
   const int plane = j.N * j.N;
   return has_resample(j) ? (plane + 255) / 256 : j.N / rows_per_det_block(j.N);
@@ -270,7 +278,8 @@ size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
   b += align_up(sizeof(JobDev) * n_jobs);                           // job table
   b += align_up(sizeof(Seg) * static_cast<size_t>(kSegsPerJob) * n_jobs);  // segment pool
   for (int i = 0; i < n_jobs; ++i) b += align_up(std::max<size_t>(jobs[i].K, 1) * sizeof(double));
-  for (int i = 0; i < n_jobs; ++i) b += czt_table_bytes(jobs[i]) + ratio_k_bytes(jobs[i]);
+  for (int i = 0; i < n_jobs; ++i)
+    b += czt_table_bytes(jobs[i]) + ratio_k_bytes(jobs[i]) + reg_bytes(jobs[i]);
   return b;
 }
 
@@ -309,6 +318,7 @@ struct Call {
   std::vector<double*> loss_k;
   std::vector<char*> czt_tab;    // per job, or null
   std::vector<double*> ratio_k;  // per job, or null
+  std::vector<float*> reg_part;  // per job
   char* chunk_base = nullptr;
   size_t chunk_bytes = 0;
   std::vector<JobDev> host_jobs;
@@ -384,6 +394,7 @@ int layout(Call& c, void* ws, size_t ws_bytes) {
   }
   c.czt_tab.assign(c.n, nullptr);
   c.ratio_k.assign(c.n, nullptr);
+  c.reg_part.assign(c.n, nullptr);
   for (int i = 0; i < c.n; ++i) {
     const size_t tb = czt_table_bytes(c.jobs[i]);
     if (tb) c.czt_tab[i] = p;
@@ -391,6 +402,8 @@ int layout(Call& c, void* ws, size_t ws_bytes) {
     const size_t rb = ratio_k_bytes(c.jobs[i]);
     if (rb) c.ratio_k[i] = reinterpret_cast<double*>(p);
     p += rb;
+    c.reg_part[i] = reinterpret_cast<float*>(p);
+    p += reg_bytes(c.jobs[i]);
   }
   if (p > end) return PTYCHO_ENOSPC;
   c.chunk_base = p;
@@ -502,6 +515,7 @@ void fill_job(Call& c, int i, char** cursor) {
   d.grad_flat[kVars] = d.g_ratio;
   d.flat_n[kVars] = j.L;
   d.ratio_k = c.ratio_k[i];
+  d.reg_part = c.reg_part[i];
   d.out = c.out ? c.out[i] : nullptr;
   d.status = c.status + i;
   d.loss_k = c.loss_k[i];
@@ -747,6 +761,12 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
 int run_epilogue(Call& c, hipStream_t s) {
   if (c.which == 0) return PTYCHO_OK;
   Phase ph;
+  auto reg = ph.begin();
+  if (c.loss.l1 != 0.f || c.loss.tv != 0.f)
+    for (int i = 0; i < c.n; ++i)
+      if (c.grads[i].loss || c.grads[i].g_object)
+        for (int sl = 0; sl < slots_of(c.jobs[i]); ++sl)
+          ph.add(reg, i, sl, static_cast<long long>(reg_blocks(c.jobs[i])));
   auto tot = ph.begin();
   for (int i = 0; i < c.n; ++i)
     if (c.grads[i].loss || c.grads[i].g_ratio) ph.add(tot, i, 0, 1);
@@ -759,7 +779,8 @@ int run_epilogue(Call& c, hipStream_t s) {
   }
   int e = upload_phase(c, ph, s);
   if (e) return e;
-  LAUNCH(KC_FINALIZE, launch_loss_total(launch_of(c, tot, 0), tot.units, c.scale, s));
+  LAUNCH(KC_FINALIZE, launch_regulariser(launch_of(c, reg, 0), reg.units, c.loss, s));
+  LAUNCH(KC_FINALIZE, launch_loss_total(launch_of(c, tot, 0), tot.units, c.loss, c.scale, s));
   LAUNCH(KC_ADAM, launch_simple(KAdam, launch_of(c, ad, 0), ad.units, s));
   return PTYCHO_OK;
 }
@@ -801,6 +822,18 @@ int run_call(Call& c, void* ws, size_t ws_bytes, hipStream_t s) {
       if (e) return e;
     }
   return run_epilogue(c, s);
+}
+
+bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.f; }
+
+int check_loss(const ptycho_loss_t& l) {
+  if (l.kind < 0 || l.kind > PTYCHO_LOSS_MIXED || !(l.eps >= 0.f) || !std::isfinite(l.scale))
+    return PTYCHO_EINVAL;
+  if (l.kind == PTYCHO_LOSS_MIXED && !(std::isfinite(l.noise_var) && l.noise_var > 0.f))
+    return PTYCHO_EINVAL;
+  if (!finite_nonneg(l.l1) || !finite_nonneg(l.tv)) return PTYCHO_EINVAL;
+  if (l.tv > 0.f && !(std::isfinite(l.tv_eps) && l.tv_eps > 0.f)) return PTYCHO_EINVAL;
+  return PTYCHO_OK;
 }
 
 // Argument checks shared by the entry points (host only, nothing touches
@@ -859,7 +892,7 @@ int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* i
   c.grads = nullptr;
   c.adam = nullptr;
   c.out = intensity;
-  c.loss = LossDev{0, 0.f, 0.f};
+  c.loss = LossDev{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
@@ -869,8 +902,8 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
   int e = common_checks(jobs, n_jobs, true);
   if (e) return e;
   if (!loss || !grads || !workspace) return PTYCHO_EINVAL;
-  if (loss->kind < 0 || loss->kind > 3 || !(loss->eps >= 0.f) || !std::isfinite(loss->scale))
-    return PTYCHO_EINVAL;
+  e = check_loss(*loss);
+  if (e) return e;
   e = init_twiddles();
   if (e) return e;
   Call c;
@@ -880,7 +913,8 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
   c.grads = grads;
   c.adam = nullptr;
   c.out = nullptr;
-  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale};
+  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale, loss->noise_var,
+                   loss->l1, loss->tv, loss->tv_eps};
   c.scale = loss->scale;
   return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
@@ -891,8 +925,8 @@ int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_
   int e = common_checks(jobs, n_jobs, true);
   if (e) return e;
   if (!loss || !grads || !adam || !workspace) return PTYCHO_EINVAL;
-  if (loss->kind < 0 || loss->kind > 3 || !(loss->eps >= 0.f) || !std::isfinite(loss->scale))
-    return PTYCHO_EINVAL;
+  e = check_loss(*loss);
+  if (e) return e;
   for (int i = 0; i < n_jobs; ++i) {
     const ptycho_adam_t& a = adam[i];
     if (a.t < 1 || !(a.beta1 >= 0.f && a.beta1 < 1.f) || !(a.beta2 >= 0.f && a.beta2 < 1.f))
@@ -915,7 +949,8 @@ int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_
   c.grads = grads;
   c.adam = adam;
   c.out = nullptr;
-  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale};
+  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale, loss->noise_var,
+                   loss->l1, loss->tv, loss->tv_eps};
   c.scale = loss->scale;
   return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }

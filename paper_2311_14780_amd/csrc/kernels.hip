@@ -128,6 +128,14 @@ __device__ __forceinline__ int col_group_of_dev(int N) { return N <= 256 ? 16 : 
 __device__ __forceinline__ int rb_adj_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 __device__ __forceinline__ int rb_det_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 
+// Mixed Poisson-Gaussian noise, Gaussian approximation with variance I + v:
+// ell = (I - m)^2 / (I + v) + ln(I + v) and its derivative in I.
+__device__ __forceinline__ void mixed_loss(float I, float m, float v, float& ell, float& dell) {
+  const float q = I + v, d = I - m, r = d / q;
+  ell = d * r + logf(q);
+  dell = 2.f * r - r * r + 1.f / q;
+}
+
 // ------------------------------------------------------- work decomposition
 // Largest s with segs[s].unit0 <= unit (segs sorted, segs[0].unit0 == 0).
 // The arguments are wave-uniform, so the search runs on the scalar unit.
@@ -601,6 +609,8 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
       } else if (loss.kind == 2) {
         ell = (I - meas) * (I - meas);
         dell = 2.f * (I - meas);
+      } else if (loss.kind == 4) {
+        mixed_loss(I, meas, loss.noise_var, ell, dell);
       } else {
         ell = meas * I;
         dell = meas;
@@ -698,6 +708,8 @@ __global__ __launch_bounds__(NT) void k_resample_loss(Launch la, LossDev loss, b
       } else if (loss.kind == 2) {
         ell = (Ip - meas) * (Ip - meas);
         dell = 2.f * (Ip - meas);
+      } else if (loss.kind == 4) {
+        mixed_loss(Ip, meas, loss.noise_var, ell, dell);
       } else {
         ell = meas * Ip;
         dell = meas;
@@ -1162,8 +1174,64 @@ __global__ void k_finalize_chunk(Launch la) {
   }
 }
 
+// ------------------------------------------------------------ regulariser
+// Amplitude a = |O| of every slot: l1 sum a + tv sum sqrt(dy^2 + dx^2 + d^2)
+// with forward differences (zero past the last row / column).  Each thread
+// owns one pixel: its value term, and its gradient
+// (l1 - tv (dy + dx) / t + tv dy_up / t_up + tv dx_left / t_left) O / a
+// (the last two from the terms of the pixels above and to the left) added to
+// g_object once per call, after every chunk's data gradient.
+// units: (job, slot) x ceil(H W / kRegBlock) pixel blocks
+__device__ __forceinline__ float amp_at(const gf2* __restrict__ O, int H, int W, int y, int x) {
+  const float2 v = ldv(O, static_cast<size_t>(y) * W + x);
+  return sqrtf(v.x * v.x + v.y * v.y);
+}
+
+__global__ __launch_bounds__(kRegBlock) void k_regulariser(Launch la, LossDev loss) {
+  __shared__ float red[kRegBlock / 64];
+  const UnitRef r = decode<1>(la);
+  const JobDev& jb = *r.jb;
+  if (*gmem(jb.status)) return;
+  const int H = jb.H, W = jb.W;
+  const size_t hw = static_cast<size_t>(H) * W;
+  const gf2* __restrict__ O = gmem(jb.object) + static_cast<size_t>(r.l) * hw;
+  const size_t p = static_cast<size_t>(r.u) * kRegBlock + threadIdx.x;
+  const float d2 = loss.tv_eps * loss.tv_eps;
+  float val = 0.f;
+  if (p < hw) {
+    const int y = static_cast<int>(p / W), x = static_cast<int>(p - static_cast<size_t>(y) * W);
+    const float2 o = ldv(O, p);
+    const float a = sqrtf(o.x * o.x + o.y * o.y);
+    const float dy = y + 1 < H ? amp_at(O, H, W, y + 1, x) - a : 0.f;
+    const float dx = x + 1 < W ? amp_at(O, H, W, y, x + 1) - a : 0.f;
+    const float t = sqrtf(dy * dy + dx * dx + d2);
+    val = loss.l1 * a + loss.tv * t;
+    float ga = loss.l1 - loss.tv * (dy + dx) / t;
+    if (y > 0) {  // term of the pixel above: its dy is a - a_up
+      const float au = amp_at(O, H, W, y - 1, x);
+      const float dxu = x + 1 < W ? amp_at(O, H, W, y - 1, x + 1) - au : 0.f;
+      const float dyu = a - au;
+      ga += loss.tv * dyu / sqrtf(dyu * dyu + dxu * dxu + d2);
+    }
+    if (x > 0) {  // term of the pixel to the left: its dx is a - a_left
+      const float al = amp_at(O, H, W, y, x - 1);
+      const float dyl = y + 1 < H ? amp_at(O, H, W, y + 1, x - 1) - al : 0.f;
+      const float dxl = a - al;
+      ga += loss.tv * dxl / sqrtf(dyl * dyl + dxl * dxl + d2);
+    }
+    if (jb.g_object && a > 0.f) {
+      gf2* __restrict__ G = gmem(jb.g_object) + static_cast<size_t>(r.l) * hw;
+      const float s = ga / a;
+      stv(G, p, cadd(ldv(G, p), make_float2(s * o.x, s * o.y)));
+    }
+  }
+  const float bs = block_sum<kRegBlock>(val, red);
+  if (threadIdx.x == 0)
+    gmem(jb.reg_part)[static_cast<size_t>(r.l) * ((hw + kRegBlock - 1) / kRegBlock) + r.u] = bs;
+}
+
 // one unit per job
-__global__ void k_loss_total(Launch la, float scale) {
+__global__ void k_loss_total(Launch la, LossDev loss, float scale) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
   if (threadIdx.x != 0) return;
@@ -1175,7 +1243,15 @@ __global__ void k_loss_total(Launch la, float scale) {
     double s = 0.0;
     const PTYCHO_GLOBAL double* lk = gmem(jb.loss_k);
     for (int k = 0; k < jb.K; ++k) s += lk[k];
-    *gmem(jb.loss) = static_cast<float>(s * scale);
+    s *= scale;
+    if (loss.l1 != 0.f || loss.tv != 0.f) {  // the regulariser, added unscaled
+      const size_t n = static_cast<size_t>(jb.L) *
+                       ((static_cast<size_t>(jb.H) * jb.W + kRegBlock - 1) / kRegBlock);
+      double rs = 0.0;
+      for (size_t i = 0; i < n; ++i) rs += gmem(jb.reg_part)[i];
+      s += rs;
+    }
+    *gmem(jb.loss) = static_cast<float>(s);
   }
   if (jb.g_ratio) {
     // dL/d alpha_l: ordered sum over positions (the terms carry the scale)
@@ -1331,9 +1407,16 @@ hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_loss_total(const Launch& la, long long units, float scale, hipStream_t s) {
+hipError_t launch_loss_total(const Launch& la, long long units, const LossDev& loss, float scale,
+                             hipStream_t s) {
   if (units <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_loss_total, grid1(units), dim3(64), 0, s, la, scale);
+  hipLaunchKernelGGL(k_loss_total, grid1(units), dim3(64), 0, s, la, loss, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_regulariser(const Launch& la, long long units, const LossDev& loss, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_regulariser, grid1(units), dim3(kRegBlock), 0, s, la, loss);
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ struct JobDev {
   float* dy_part;       // [C][L][N / G]
   float* sg_part;       // [C][L][N / G]
   float* dx_part;       // [C][L][N / RBadj]
+  float* reg_part;      // [L][ceil(H W / 256)] regulariser value per pixel block
   float* ra_part;       // [C][L][N / RBdet] alpha-derivative terms of the detector rows
   float* rb_part;       // [C][L][N / G]     alpha-derivative terms of the columns
   float* ibuf;          // [C][N][N] (resampling only) I + B, then R^T g
@@ -109,7 +110,9 @@ struct Launch {
 struct LossDev {
   int kind;
   float eps;
-  float gscale;  // 2 * scale: folds the factor of G_Psi = 2 g Psi
+  float gscale;     // 2 * scale: folds the factor of G_Psi = 2 g Psi
+  float noise_var;  // read-noise variance of the mixed-noise loss
+  float l1, tv, tv_eps;  // amplitude regularisers
 };
 
 // Kernel-argument payload of the table writer.
@@ -152,7 +155,11 @@ size_t col_adj_lds_of(int N, int M, int group);
 // units of the launch's segments.
 hipError_t launch_write_table(int* dst, const int* data, int n, hipStream_t s);
 hipError_t launch_simple(int kind, const Launch& la, long long units, hipStream_t s);
-hipError_t launch_loss_total(const Launch& la, long long units, float scale, hipStream_t s);
+hipError_t launch_loss_total(const Launch& la, long long units, const LossDev& loss, float scale,
+                             hipStream_t s);
+// Amplitude L1 / TV regulariser: value per pixel block, gradient into g_object.
+hipError_t launch_regulariser(const Launch& la, long long units, const LossDev& loss, hipStream_t s);
+constexpr int kRegBlock = 256;  // pixels per regulariser block
 hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t s);
 hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s);
 // mode: 0 fused loss + adjoint, 1 forward (I + B to ibuf or out; `spill`

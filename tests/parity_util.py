@@ -117,7 +117,7 @@ def to_problem(case, device):
 
 
 def gpu_grads(prob, kind=0, eps=1e-6, scale=1.0, chunk=0,
-              want=("object", "probe", "pos", "sigma", "background"), stream=None):
+              want=("object", "probe", "pos", "sigma", "background"), stream=None, **reg):
     import torch
     from paper_2311_14780_amd import binding as B
     dev = prob.object.device
@@ -135,7 +135,8 @@ def gpu_grads(prob, kind=0, eps=1e-6, scale=1.0, chunk=0,
     if "ratio" in want:
         g["g_ratio"] = torch.zeros(prob.L, device=dev)
     ws = B.workspace([prob], 1, chunk)
-    B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws, stream=stream)
+    B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws, stream=stream,
+                       **reg)
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in g.items()}
     out["loss"] = float(out["loss"][0])

@@ -239,3 +239,18 @@ def test_sample_modes_scale_the_per_position_workspace():
     b2 = _ws_bytes(j2, chunk=4)[1]
     # X, GX and Y grow with the slot count (L Ns)
     assert b2 - b1 >= 4 * 8 * 64 * 64 * 2 * (2 + 3)
+
+
+@pytest.mark.parametrize("fields", [
+    dict(kind=5), dict(kind=4, noise_var=0.0), dict(kind=4, noise_var=float("nan")),
+    dict(l1=-1.0), dict(tv=1.0, tv_eps=0.0), dict(tv=float("inf"))])
+def test_invalid_loss_parameters_rejected_on_host(fields):
+    j = _job()
+    kw = dict(kind=0, eps=1e-6, scale=1.0, noise_var=1.0, l1=0.0, tv=0.0, tv_eps=1e-3)
+    kw.update(fields)
+    loss = B.LossT(kw["kind"], kw["eps"], kw["scale"], kw["noise_var"], kw["l1"], kw["tv"],
+                   kw["tv_eps"])
+    grads = B.GradsT()
+    rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
+                                  ctypes.c_void_p(0x2000), 1 << 20, None)
+    assert rc == B.PTYCHO_EINVAL
