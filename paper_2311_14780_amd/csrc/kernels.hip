@@ -826,13 +826,17 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
       return u < N ? ldv(Zm, u * N + line) : make_float2(0.f, 0.f);
     }
   };
+  // The next mode's first-pass inputs are loaded during the current mode in
+  // the single-position zero-padded instances; the grouped and the
+  // exact-ratio (length 2N) instances have no registers left for them.
+  constexpr bool PREFETCH = !GROUPED && !CZT;
   using ZIn = PreIn<NL, G, CNT, true>;
   auto zload = [&](int m, ZIn& zin) {
     const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
     fft_first_load(zin, [&](int line, int t) { return zin_at(Zm, line, t); });
   };
   ZIn zcur;
-  if constexpr (!GROUPED) zload(0, zcur);
+  if constexpr (PREFETCH) zload(0, zcur);
   for (int m = 0; m < jb.M; ++m) {
     gf2* __restrict__ Z = Z0 + static_cast<size_t>(m) * N * N;
     const gf2* __restrict__ P =
@@ -864,7 +868,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
         __syncthreads();
       }
     }
-    if constexpr (GROUPED) {
+    if constexpr (!PREFETCH) {
       auto ld_z = [&](int line, int t) { return zin_at(Z, line, t); };
       if constexpr (CZT) {
         fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_z, st_hc);
@@ -875,12 +879,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
     } else {
       ZIn znext;
       if (m + 1 < jb.M) zload(m + 1, znext);
-      if constexpr (CZT) {
-        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, zcur, st_hc);
-        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
-      } else {
-        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
-      }
+      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
       zcur = znext;
     }
 #pragma unroll
