@@ -2,7 +2,9 @@
 
 ``PtychoLoss`` returns the scalar loss of Eq. 1's model against the measured
 patterns; its backward multiplies the library's hand-written gradients
-(object, probe, positions, power coefficients) by the incoming gradient.
+(object, probe, positions, power coefficients, background and, for a tensor
+of exact sampling ratios, dL/d alpha, i.e. the propagation distance) by the
+incoming gradient.
 The forward call already computes the gradients (one fused pass), so the
 backward is a scaling only.
 
@@ -22,8 +24,13 @@ import torch
 from . import binding as B
 
 
+_KEYS = ("g_object", "g_probe", "g_pos", "g_sigma", "g_background", "g_ratio")
+
+
 def _zeros_like_grads(problem: B.Problem, need):
+    """need: flags for object, probe, positions, sigma, background, ratio."""
     dev = problem.object.device
+    need = tuple(need) + (False,) * (6 - len(need))
     g = dict(loss=torch.zeros(1, device=dev))
     if need[0]:
         g["g_object"] = torch.zeros_like(problem.object)
@@ -33,7 +40,18 @@ def _zeros_like_grads(problem: B.Problem, need):
         g["g_pos"] = torch.zeros(problem.K, 2, device=dev)
     if need[3]:
         g["g_sigma"] = torch.zeros(problem.K, device=dev)
+    if need[4]:
+        g["g_background"] = torch.zeros(problem.N, problem.N, device=dev)
+    if need[5]:
+        g["g_ratio"] = torch.zeros(problem.L, device=dev)
     return g
+
+
+def _pads_of(pads, ratio):
+    """A tensor of exact ratios (floats) replaces the pads."""
+    if ratio is None:
+        return tuple(pads)
+    return tuple(float(a) for a in ratio.detach().cpu().tolist())
 
 
 class _Workspace:
@@ -54,37 +72,45 @@ _WS = _Workspace()
 
 class PtychoLossFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, obj, probe, pos, sigma, pads, measured, background, mask, resample,
-                kind, eps, scale, chunk):
+    def forward(ctx, obj, probe, pos, sigma, background, ratio, measured, mask, resample, pads,
+                kind, eps, scale, chunk, reg):
         prob = B.Problem(object=obj.detach().contiguous(), probe=probe.detach().contiguous(),
-                         pos=pos.detach().contiguous(), pads=tuple(pads),
+                         pos=pos.detach().contiguous(), pads=_pads_of(pads, ratio),
                          measured=measured.contiguous(),
                          sigma=None if sigma is None else sigma.detach().contiguous(),
-                         background=background, mask=mask, resample=resample)
-        need = tuple(ctx.needs_input_grad[:3]) + (sigma is not None and ctx.needs_input_grad[3],)
+                         background=None if background is None else background.detach().contiguous(),
+                         mask=mask, resample=resample)
+        ng = ctx.needs_input_grad
+        need = (ng[0], ng[1], ng[2], sigma is not None and ng[3],
+                background is not None and ng[4], ratio is not None and ng[5])
         g = _zeros_like_grads(prob, need)
         ws = _WS.get(prob, 1, chunk)
-        B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws)
-        ctx.save_for_backward(*(g.get(k) for k in ("g_object", "g_probe", "g_pos", "g_sigma")
-                                if g.get(k) is not None))
-        ctx.have = tuple(g.get(k) is not None for k in ("g_object", "g_probe", "g_pos", "g_sigma"))
+        B.ptycho_loss_grad([prob], [g], kind=kind, eps=eps, scale=scale, workspace=ws, **reg)
+        ctx.save_for_backward(*(g[k] for k in _KEYS if k in g))
+        ctx.have = tuple(k in g for k in _KEYS)
+        ctx.ratio_like = None if ratio is None else (ratio.device, ratio.dtype)
         return g["loss"][0]
 
     @staticmethod
     def backward(ctx, gout):
         saved = list(ctx.saved_tensors)
-        out = []
-        for have in ctx.have:
-            out.append(saved.pop(0) * gout if have else None)
-        return (out[0], out[1], out[2], out[3]) + (None,) * 9
+        out = [saved.pop(0) * gout if have else None for have in ctx.have]
+        if out[5] is not None:  # the ratios may be host data
+            out[5] = out[5].to(device=ctx.ratio_like[0], dtype=ctx.ratio_like[1])
+        return tuple(out) + (None,) * 9
 
 
 def ptycho_loss(obj, probe, pos, pads, measured, sigma=None, background=None, mask=None,
                 resample=None, kind: int = B.LOSS_AMPLITUDE, eps: float = 1e-6,
-                scale: float = 1.0, chunk: int = 0) -> torch.Tensor:
-    """Scalar loss (differentiable w.r.t. obj, probe, pos and sigma)."""
-    return PtychoLossFn.apply(obj, probe, pos, sigma, tuple(pads), measured, background, mask,
-                              resample, int(kind), float(eps), float(scale), int(chunk))
+                scale: float = 1.0, chunk: int = 0, ratio: Optional[torch.Tensor] = None,
+                **reg) -> torch.Tensor:
+    """Scalar loss, differentiable w.r.t. obj, probe, pos, sigma, background and
+    ``ratio`` (a tensor of exact sampling ratios alpha_l that replaces ``pads``;
+    alpha_l is proportional to the propagation distance z).  ``reg``:
+    noise_var (mixed-noise loss), l1, tv, tv_eps (amplitude regularisers)."""
+    return PtychoLossFn.apply(obj, probe, pos, sigma, background, ratio, measured, mask,
+                              resample, tuple(pads), int(kind), float(eps), float(scale),
+                              int(chunk), dict(reg))
 
 
 class PtychoForwardFn(torch.autograd.Function):

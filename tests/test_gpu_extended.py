@@ -201,3 +201,29 @@ def test_c2_full_size_at_bench_configuration():
     got = U.gpu_grads(prob)
     ref = U.oracle_grads(case, workers=nw)
     print("C2 full grads", U.compare(got, ref))
+
+
+def test_autograd_background_distance_and_regularisers():
+    # torch autograd through the library: background and the exact ratios
+    # (alpha proportional to the propagation distance) as differentiable inputs
+    from paper_2311_14780_amd import autograd as A
+    w = synth.reduced(synth.get_workload("C1"), L=2, M=2, harmonics=(19, 23),
+                      mode_weights=(0.75, 0.25), K=8, name="C1-ag")
+    ratios = synth.ratios_for(w.N, w.harmonics, w.ref_harmonic)
+    case = U.make_case(w, pads=ratios, with_bg=True)
+    reg = dict(l1=0.01, tv=0.2, tv_eps=0.05)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    obj = t(case["obj"]).requires_grad_()
+    prb = t(case["prb"]).requires_grad_()
+    pos = t(case["pos"])
+    bg = t(case["bg"]).requires_grad_()
+    ratio = torch.tensor(ratios, dtype=torch.float64, requires_grad=True)
+    loss = A.ptycho_loss(obj, prb, pos, (0, 0), t(case["meas"]), background=bg, ratio=ratio,
+                         kind=1, **reg)
+    loss.backward()
+    ref = U.oracle_grads(case, kind=1, **reg)
+    got = {"loss": float(loss.item()), "g_object": obj.grad.cpu().numpy(),
+           "g_probe": prb.grad.cpu().numpy(), "g_background": bg.grad.cpu().numpy(),
+           "g_ratio": ratio.grad.numpy()}
+    assert ratio.grad.dtype == torch.float64
+    print("autograd bg/ratio/reg", U.compare(got, ref))
