@@ -544,14 +544,14 @@ DEFAULT_TICK_CAP = 2 * 4800 * 256 * 256
 def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2.0,
                budget_bytes: Optional[int] = None, workspace_bytes: int = 8 << 30,
                device="cuda:0", log=print, tick_cap: Optional[int] = DEFAULT_TICK_CAP,
-               policy: str = "hybrid", depth: int = 2) -> dict:
+               policy: str = "hybrid", depth: int = 2, exact_fraction: float = 0.0) -> dict:
     """The serving stream end to end: job mix, data, service-time probe,
     Poisson arrivals at ``load`` times the sequential service rate, then the
     continuous-batching run and the first-come first-served sequential run
     over the same arrivals."""
     import torch
     import synth.serving as SS
-    wl = SS.serving_jobs(n_jobs, seed)
+    wl = SS.serving_jobs(n_jobs, seed, exact_fraction=exact_fraction)
     t0 = time.perf_counter()
     hosts = host_jobs(wl)
     log(f"host data of {n_jobs} jobs: {time.perf_counter() - t0:.1f} s")
@@ -577,6 +577,7 @@ def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2
            "mean_arrival_gap_s": round(gap, 5), "budget_bytes": int(budget_bytes),
            "workspace_bytes": int(workspace_bytes), "tick_cap_pattern_pixels": tick_cap,
            "policy": policy, "pipeline_depth": depth,
+           "exact_ratio_jobs": int(sum(w.exact_ratio for w in wl)),
            "pattern_modes_total": int(iters * sum(r.pattern_modes for r in reqs))}
     for mode in ("batch", "sequential"):
         sch = Scheduler(ex, budget_bytes, log=log, tick_cap=tick_cap, policy=policy, depth=depth)
@@ -605,11 +606,13 @@ if __name__ == "__main__":
                     help="pattern-pixels (K L M N^2) per fused call; 0: no cap")
     ap.add_argument("--policy", default="hybrid", choices=POLICIES)
     ap.add_argument("--depth", type=int, default=2, help="fused calls in flight")
+    ap.add_argument("--exact-fraction", type=float, default=0.0,
+                    help="fraction of jobs using the exact-ratio propagator")
     a = ap.parse_args()
     res = run_stream(a.jobs, a.iters, a.seed, a.load,
                      None if a.budget_gb <= 0 else int(a.budget_gb * 1e9),
                      int(a.workspace_gb * (1 << 30)),
                      log=lambda s: print(s, flush=True),
                      tick_cap=int(a.tick_cap) if a.tick_cap > 0 else None, policy=a.policy,
-                     depth=a.depth)
+                     depth=a.depth, exact_fraction=a.exact_fraction)
     print(json.dumps(res), flush=True)

@@ -35,6 +35,7 @@ class Workload:
     scan_jitter: float = 0.0    # uniform half-width or Gaussian sigma (px)
     scan_origin: float = 0.0    # raster origin (px)
     raster_side: int = 0        # raster is raster_side x raster_side
+    exact_ratio: bool = False   # propagate at the exact wavelength ratios (not smooth pads)
     note: str = ""
 
     @property

@@ -86,8 +86,9 @@ def make_truth(w, Ns: int | None = None) -> dict:
 
     Returns a dict with complex128 ``object`` [L][Ns][H][W], complex128
     ``probe`` [L][M][N][N], float32 ``pos`` [K][2] (y, x top-left of the
-    window in object pixels), ``pads`` (N_l per wavelength), ``ratios`` (the
-    exact sampling ratio per wavelength, floats), ``sigma`` /
+    window in object pixels), ``pads`` (N_l per wavelength; the exact ratios
+    when the workload asks for them), ``ratios`` (the exact sampling ratio
+    per wavelength, floats), ``sigma`` /
     ``background`` / ``mask`` (None: all ones / zero / all valid).
     """
     rng = np.random.Generator(np.random.PCG64(w.seed))
@@ -99,6 +100,8 @@ def make_truth(w, Ns: int | None = None) -> dict:
                  pads=pads_for(w.N, w.harmonics, w.ref_harmonic),
                  ratios=ratios_for(w.N, w.harmonics, w.ref_harmonic),
                  sigma=None, background=None, mask=None, resample=None)
+    if w.exact_ratio:
+        truth["pads"] = truth["ratios"]
     if w.tilt:
         from .tilt import tilt_table
         idx, wt, mask = tilt_table(w.N)

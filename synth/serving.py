@@ -20,8 +20,10 @@ import numpy as np
 from .configs import SERVING_HARMONICS, SERVING_SIZES, Workload, _geometric_weights
 
 
-def serving_workload(job: int, N: int, L: int, M: int, K: int, seed: int) -> Workload:
-    """The workload of one serving job (object side from the spiral extent)."""
+def serving_workload(job: int, N: int, L: int, M: int, K: int, seed: int,
+                     exact_ratio: bool = False) -> Workload:
+    """The workload of one serving job (object side from the spiral extent;
+    ``exact_ratio``: propagate at the exact wavelength ratios)."""
     c = 0.075 * N
     side = 2.0 * c * math.sqrt(max(K - 1, 1)) + N + 2.0
     H = W = int(math.ceil(side / 64.0) * 64)
@@ -29,22 +31,26 @@ def serving_workload(job: int, N: int, L: int, M: int, K: int, seed: int) -> Wor
     return Workload(
         name=f"job{job}", K=K, L=L, M=M, N=N, H=H, W=W,
         harmonics=harm, ref_harmonic=harm[0], mode_weights=_geometric_weights(M),
-        photons=1e5, scan="spiral", seed=seed,
+        photons=1e5, scan="spiral", seed=seed, exact_ratio=exact_ratio,
         note="serving job",
     )
 
 
 def serving_jobs(n_jobs: int = 64, seed: int = 4, sizes=SERVING_SIZES, L_max: int = 5,
-                 M_max: int = 8, K_range=(100, 1600)) -> list:
-    """The job mix: a list of Workloads, job j seeded with seed * 1000 + j."""
+                 M_max: int = 8, K_range=(100, 1600), exact_fraction: float = 0.0) -> list:
+    """The job mix: a list of Workloads, job j seeded with seed * 1000 + j.
+    A fraction ``exact_fraction`` of the jobs (drawn from a stream of its own,
+    so the sizes do not change with it) uses the exact-ratio propagator."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rng_x = np.random.Generator(np.random.PCG64(seed + 555))
     jobs = []
     for j in range(n_jobs):
         N = int(rng.choice(np.asarray(sizes)))
         L = int(rng.integers(1, L_max + 1))
         M = int(rng.integers(1, M_max + 1))
         K = int(rng.integers(K_range[0], K_range[1] + 1))
-        jobs.append(serving_workload(j, N, L, M, K, seed * 1000 + j))
+        exact = bool(rng_x.uniform() < exact_fraction)
+        jobs.append(serving_workload(j, N, L, M, K, seed * 1000 + j, exact))
     return jobs
 
 

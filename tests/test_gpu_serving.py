@@ -25,8 +25,11 @@ class TickClock:
 
 def _requests(iters):
     from paper_2311_14780_amd import serving as S
-    specs = [(128, 2, 3, 14), (256, 1, 2, 6), (128, 3, 1, 9), (128, 1, 4, 11), (256, 2, 1, 5)]
-    wl = [SS.serving_workload(j, N, L, M, K, 900 + j) for j, (N, L, M, K) in enumerate(specs)]
+    # jobs 2 and 4 use the exact-ratio propagator (their own launch groups
+    # inside the same fused calls)
+    specs = [(128, 2, 3, 14, False), (256, 1, 2, 6, False), (128, 3, 1, 9, True),
+             (128, 1, 4, 11, False), (256, 2, 1, 5, True)]
+    wl = [SS.serving_workload(j, N, L, M, K, 900 + j, x) for j, (N, L, M, K, x) in enumerate(specs)]
     hosts = S.host_jobs(wl, workers=1)
     # arrivals in ticks: two at once, then one joining each of the next ticks
     return S.build_requests(wl, hosts, [0.0, 0.0, 1.0, 2.5, 4.0], iters, DEV)
