@@ -121,3 +121,11 @@ def test_benchmark_workload_exact_ratios_full_size():
     ks = [0, 199, 399]
     I_gpu, got = _run(case, ks, ws_gb=2)
     _check(case, ks, I_gpu, got)
+
+
+def test_reflection_workload_exact_ratios_full_size():
+    # N = 384, Bluestein length 768, tilt table, 900 positions
+    case = _case("C5", 52, exact_ratio=True)
+    ks = [0, 450, 899]
+    I_gpu, got = _run(case, ks, ws_gb=8)
+    _check(case, ks, I_gpu, got)
