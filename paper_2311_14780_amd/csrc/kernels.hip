@@ -6,8 +6,8 @@
 //   col_fwd   : y-shift of X columns, times sigma P_{l,m} for every mode,
 //               first (column) pass of the padded, cropped DFT            -> Y
 //   det       : second (row) pass of the DFT, incoherent sum over l and m,
-//               background, loss and its derivative, 2 g Psi, adjoint row
-//               DFT                                                        -> Z (in Y)
+//               background, loss and its derivative, then per plane the far
+//               field again from Y (not stored), 2 g Psi, adjoint row DFT  -> Z (in Y)
 //   col_adj   : adjoint column DFT -> chi; G_Osh = sum_m conj(sigma P) chi;
 //               probe-gradient terms conj(sigma Osh) chi (in Y); sigma and
 //               y-position derivatives; adjoint y-shift                  -> GX
@@ -16,6 +16,11 @@
 //   obj_gather: object gradient tiles gather G_A of every overlapping window
 //               in ascending k (no atomics)
 //   finalize  : ordered per-position sums of the partials
+// Optional stages: chirp tables of the exact-ratio propagator (Bluestein,
+// FFT length 2N, at the start of a call), the background-gradient sum, the
+// alpha-derivative terms (detector and column adjoint), the amplitude
+// regulariser (once per call, after the data gradient).  Wavelengths and
+// sample modes are "slots" s = l Ns + n; the probe of slot s is P_{s / Ns}.
 // The C ABI (api.cpp) sequences these launches on one stream.
 //
 // Every launch covers the work of one or more jobs: the job descriptors live
@@ -417,29 +422,12 @@ __device__ __noinline__ void det_rows_fwd(lf2* buf, lf32* acc, gf2* __restrict__
   fft_lines<NL, false, RB, NT, LP, false>(buf, twL, ld, st);
 }
 
-// Adjoint row pass: Z[u][:] = (1/sqrt(NL)) DFT^H_NL_x( embed( g2 Psi[u][:] ) )[0:N],
-// g2 = acc (2 scale w dloss/dI), written over Psi.
-template <int N, int NL, int RB>
-__device__ __noinline__ void det_rows_adj(lf2* buf, const lf32* acc, gf2* __restrict__ Yr,
-                                          const gf2* __restrict__ twL, float ps) {
-  constexpr int LP = row_lp(NL);
-  auto ld = [&](int line, int t) {
-    int u = t + N / 2;
-    if (u >= NL) u -= NL;
-    return u < N ? cscale(ldv(Yr, line * N + u), acc[line * N + u]) : make_float2(0.f, 0.f);
-  };
-  auto st = [&](int line, int t, float2 v) {
-    if (t < N) stv(Yr, line * N + t, cscale(v, ps));
-  };
-  fft_lines<NL, true, RB, NT, LP, false>(buf, twL, ld, st);
-}
-
-// Zero-padded adjoint row pass of the fused kernel (MODE 0): recomputes
-// Psi = crop(DFT(Y)) from the kept column output instead of reading a stored
-// Psi, scales by g2 in LDS and applies the adjoint transform, written over Y.
-// One more row transform, and one plane written and read less per (l, m):
-// neutral where the kernel is issue-bound, faster where it is HBM-bound
-// (N = 512, M = 8: 205 -> 188 ms per step).
+// Zero-padded adjoint row pass: recomputes Psi = crop(DFT(Y)) from the kept
+// column output instead of reading a stored Psi, scales by g2 in LDS and
+// applies the adjoint transform Z[u][:] = (1/sqrt(NL)) DFT^H(embed(g2 Psi))[0:N],
+// written over Y.  One more row transform, and one plane written and read
+// less per (l, m): neutral where the kernel is issue-bound, faster where it
+// is HBM-bound (N = 512, M = 8: 205 -> 188 ms per step).
 template <int N, int NL, int RB>
 __device__ __noinline__ void det_rows_recomp(lf2* buf, const lf32* acc, gf2* __restrict__ Yr,
                                              const gf2* __restrict__ twL, float ps) {
@@ -597,10 +585,10 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
       const float ps = jb.pad_scale[l];
       const float2* twL = jb.tw_pad[l];
       const int nl = jb.pad[l];
-      // Psi is kept for the adjoint (resampling split, exact-ratio rows),
-      // except where the adjoint recomputes it (fused zero-padded rows, and
-      // exact-ratio rows of jobs that want dL/d alpha)
-      const bool keep = (((MODE == 0) && jb.czt[l]) || (MODE == 1 && spill)) &&
+      // Psi is kept for the adjoint only on exact-ratio rows (whose recompute
+      // costs two transforms) of jobs that do not want dL/d alpha; zero-padded
+      // rows keep Y and the adjoint recomputes Psi from it
+      const bool keep = ((MODE == 0) || (MODE == 1 && spill)) && jb.czt[l] &&
                         !(jb.g_ratio && jb.czt[l]);
       for (int m = 0; m < jb.M; ++m) {
         gf2* Yr = gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * plane +
@@ -684,10 +672,8 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
           } else {
             det_rows_adj_czt<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]));
           }
-        } else if (MODE == 0) {
-          det_rows_recomp<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
         } else {
-          det_rows_adj<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
+          det_rows_recomp<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
         }
       }, Rows{});
     }

@@ -163,7 +163,8 @@ constexpr int kRegBlock = 256;  // pixels per regulariser block
 hipError_t launch_row_fwd(int N, const Launch& la, long long units, hipStream_t s);
 hipError_t launch_col_fwd(int N, int nl, const Launch& la, long long units, hipStream_t s);
 // mode: 0 fused loss + adjoint, 1 forward (I + B to ibuf or out; `spill`
-// keeps Psi for mode 2), 2 adjoint from ibuf (R^T g), 3 loss only.
+// keeps Psi of exact-ratio rows for mode 2; zero-padded rows keep Y and the
+// adjoint recomputes Psi), 2 adjoint from ibuf (R^T g), 3 loss only.
 // var: 0 zero-padded DFTs only; 1 some wavelength uses the exact-ratio
 // propagator (LDS rows of length 2N); 2 as 1, and the jobs want dL/d alpha
 // (modes 0 and 2: the adjoint recomputes Psi and the alpha-derivative terms)
