@@ -123,6 +123,85 @@ def build_inputs(w, device, exact_ratio: bool = False):
     return truth, start, prob
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+_POOL_DATA = None
+
+
+def _pool_init(data):
+    """Initializer of the all-cores baseline's workers: the inputs, once."""
+    global _POOL_DATA
+    _POOL_DATA = data
+
+
+def _oracle_positions(ks):
+    """Worker of the all-cores baseline: loss + gradients of some positions."""
+    import oracle
+    obj, prb, pos, pads, meas, mask, table = _POOL_DATA
+    for k in ks:
+        oracle.loss_grad(obj, prb, pos, pads, meas, mask=mask, resample_table=table, positions=[k])
+    return len(ks)
+
+
+def cpu_baseline_pool(w, truth, start, workers: int, per_worker: int = 16,
+                      timeout_s: float = 600.0):
+    """The same oracle over a pool of processes (one BLAS thread each) on the
+    host's cores: ``per_worker`` positions per worker, wall time of the pool.
+    The pool is terminated if it has not finished within ``timeout_s``."""
+    import oracle
+    import synth
+    import multiprocessing as mp
+    n = workers * per_worker
+    obj = start["object"].astype(np.complex64).astype(np.complex128)
+    prb = start["probe"].astype(np.complex64).astype(np.complex128)
+    I = oracle.forward(truth["object"], truth["probe"], truth["pos"][:n], truth["pads"],
+                       resample_table=truth["resample"])
+    meas = synth.sample_counts(I, w.seed)
+    common = (obj, prb, start["pos"][:n], start["pads"], meas, truth["mask"], truth["resample"])
+    parts = [list(range(i, n, workers)) for i in range(workers)]
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"  # inherited by the workers
+    pool = mp.get_context("spawn").Pool(workers, initializer=_pool_init, initargs=(common,))
+    try:
+        pool.map_async(_oracle_positions, [[0]] * workers, chunksize=1).get(timeout_s)  # warm-up
+        t0 = time.perf_counter()
+        done = sum(pool.map_async(_oracle_positions, parts, chunksize=1).get(timeout_s))
+        elapsed = time.perf_counter() - t0
+    finally:
+        pool.terminate()
+        pool.join()
+    pm = done * w.L * w.M * w.Ns
+    return dict(value=pm / elapsed, unit="pattern-modes/s", cores=workers, kind="oracle",
+                sample=(f"{done} of {w.K} positions of {w.name}, {workers} processes of one "
+                        f"thread, {elapsed:.1f} s wall; {cpu_model()}"))
+
+
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Measured device-to-device copy bandwidth (GB/s, read + write bytes)."""
+    import torch
+    a = torch.empty(mib * 2**18, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2.0 * mib * 2**20 / sec / 1e9
+
+
 def cpu_baseline(w, truth, start, budget_s: float = 12.0, max_positions: int = 256):
     """FP64 oracle loss + gradient on the first positions of the workload,
     one position at a time until the time budget is spent."""
@@ -150,7 +229,8 @@ def cpu_baseline(w, truth, start, budget_s: float = 12.0, max_positions: int = 2
     return dict(value=pm / elapsed, unit="pattern-modes/s", cores=1, kind="oracle",
                 sample=(f"{done} of {w.K} positions of {w.name} at full N/L/M, amplitude loss + "
                         f"object/probe/position/sigma gradients, FP64 NumPy ({prop}), one "
-                        f"thread, {elapsed:.1f} s; host has {os.cpu_count()} logical CPUs"))
+                        f"thread, {elapsed:.1f} s; host has {os.cpu_count()} logical CPUs, "
+                        f"{cpu_model()}"))
 
 
 def copy_calibration(mib: int) -> int:
@@ -182,12 +262,25 @@ def main(argv=None):
     ap.add_argument("--propagator", choices=("pad", "czt"), default="pad",
                     help="pad: zero-padded DFT at the smooth pad sizes; czt: exact-ratio "
                          "propagator (scaled DFT by Bluestein's method)")
+    ap.add_argument("--cpu-pool", type=int, default=0, metavar="WORKERS",
+                    help="only time the oracle over a pool of WORKERS processes on the host "
+                         "(no GPU use) and print it as one JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args(argv)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.cpu_pool:
+        import synth
+        w = synth.get_workload(args.workload)
+        truth = synth.make_truth(w)
+        if args.propagator == "czt":
+            truth["pads"] = truth["ratios"]
+        start = synth.make_start(truth, w)
+        print(json.dumps({"cpu_baseline_pool": cpu_baseline_pool(w, truth, start, args.cpu_pool),
+                          "workload": w.name, "propagator": args.propagator}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU position-sharded design is not built)", file=sys.stderr)
@@ -265,6 +358,7 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, truth, start)
+    copy_gbps = copy_bandwidth()
     serving = None
     pads = [round(p, 4) if isinstance(p, float) else int(p) for p in prob.pads]
     prop = ("exact-ratio propagator (scaled DFT by Bluestein's method, FFT length 2N), ratios "
@@ -292,6 +386,8 @@ def main(argv=None):
                           "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "context": {"device_copy_GBps": round(copy_gbps, 1),
+                    "note": "torch device-to-device copy of 1 GiB, read + write bytes"},
         "serving": serving,
         "kernels": kern_out,
     }

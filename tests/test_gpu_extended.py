@@ -29,10 +29,12 @@ def test_c5_tilt_table_positions_full_shapes():
 
 
 def test_c3_shapes_reduced_positions():
-    case = U.make_case(synth.get_workload("C3"), K=2)
+    # 16 positions at the full N / L / M of the large multiplexed workload,
+    # several chunks per call
+    case = U.make_case(synth.get_workload("C3"), K=16, workers=U.default_workers())
     prob = U.to_problem(case, DEV)
-    got = U.gpu_grads(prob, chunk=1)
-    print("C3(K=2) grads", U.compare(got, U.oracle_grads(case)))
+    got = U.gpu_grads(prob, chunk=5)
+    print("C3(K=16) grads", U.compare(got, U.oracle_grads(case, workers=U.default_workers())))
 
 
 def test_vjp_mode_matches_oracle():
