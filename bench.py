@@ -184,6 +184,39 @@ def cpu_baseline_pool(w, truth, start, workers: int, per_worker: int = 16,
                         f"thread, {elapsed:.1f} s wall; {cpu_model()}"))
 
 
+def graph_timing(B, prob, g, ws, steps: int, warmup: int) -> dict:
+    """Loss + gradient call (no Adam: a captured step would replay its Adam
+    step number) eager and replayed from a captured HIP graph, ms per call."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    call = lambda: B.ptycho_loss_grad([prob], [g], kind=B.LOSS_AMPLITUDE, eps=1e-6, scale=1.0,
+                                      workspace=ws, stream=s)
+    with torch.cuda.stream(s):
+        for _ in range(max(warmup, 1)):
+            call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            call()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) * 1e3 / steps
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        call()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    replay = (time.perf_counter() - t0) * 1e3 / steps
+    del graph
+    return {"eager_ms_per_call": round(eager, 4), "graph_ms_per_call": round(replay, 4),
+            "note": "loss + gradient call, eager vs replayed from one captured graph"}
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     """Measured device-to-device copy bandwidth (GB/s, read + write bytes)."""
     import torch
@@ -262,6 +295,9 @@ def main(argv=None):
     ap.add_argument("--propagator", choices=("pad", "czt"), default="pad",
                     help="pad: zero-padded DFT at the smooth pad sizes; czt: exact-ratio "
                          "propagator (scaled DFT by Bluestein's method)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the loss + gradient call replayed from a captured HIP graph "
+                         "(launch overhead of small workloads); reported as graph_ms_per_call")
     ap.add_argument("--cpu-pool", type=int, default=0, metavar="WORKERS",
                     help="only time the oracle over a pool of WORKERS processes on the host "
                          "(no GPU use) and print it as one JSON line")
@@ -355,6 +391,9 @@ def main(argv=None):
             b = alg_bytes(name, K, L, M, N, H, W)
             if b:
                 d["alg_GBps"] = round(b / (d["ms_per_step"] * 1e-3) / 1e9, 1)
+    graph = None
+    if args.graph:
+        graph = graph_timing(B, prob, g, ws, args.steps, args.warmup)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, truth, start)
@@ -386,6 +425,7 @@ def main(argv=None):
                           "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "graph": graph,
         "context": {"device_copy_GBps": round(copy_gbps, 1),
                     "note": "torch device-to-device copy of 1 GiB, read + write bytes"},
         "serving": serving,
