@@ -271,7 +271,12 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
   return b;
 }
 
-constexpr int kSegsPerJob = 72;  // bound on the segments one job adds to one phase
+// Bound on the segments one job adds to one phase: a chunk iteration adds
+// 5 per slot (row forward, column forward, column adjoint, row adjoint,
+// object gather), one per wavelength (probe reduction) and 4 more.
+constexpr int kSegsPerJob = 5 * kMaxL + PTYCHO_MAX_WAVELENGTHS + 4;
+static_assert(kSegsPerJob >= 2 * PTYCHO_MAX_WAVELENGTHS + kVars + 3,
+              "the prologue's segments (gradients, status, checks, chirp tables) fit too");
 
 size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
   size_t b = align_up(sizeof(int) * n_jobs);                        // status

@@ -77,3 +77,15 @@ def test_sample_modes_chunk_invariance():
     b = U.gpu_grads(prob, chunk=4)
     for k in ("loss", "g_object", "g_probe", "g_pos", "g_sigma", "g_background"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_sixteen_slots():
+    # 8 wavelengths x 2 sample modes: the largest slot count of a job
+    harm = (17, 18, 19, 20, 21, 22, 23, 24)
+    w = synth.reduced(synth.get_workload("C1"), L=8, M=1, Ns=2, harmonics=harm,
+                      ref_harmonic=24, mode_weights=(1.0,), K=4, name="C1-16slots")
+    pads = (96, 90, 84, 80, 72, 72, 64, 64)  # compiled sizes for N = 64
+    case = U.make_case(w, pads=pads, with_bg=True)
+    prob = U.to_problem(case, DEV)
+    got = U.gpu_grads(prob, chunk=2)
+    print("16 slots", pads, U.compare(got, U.oracle_grads(case)))
