@@ -115,17 +115,21 @@ def ptycho_loss(obj, probe, pos, pads, measured, sigma=None, background=None, ma
 
 class PtychoForwardFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, obj, probe, pos, sigma, pads, background, mask, resample, chunk):
+    def forward(ctx, obj, probe, pos, sigma, background, ratio, pads, mask, resample, chunk):
         prob = B.Problem(object=obj.detach().contiguous(), probe=probe.detach().contiguous(),
-                         pos=pos.detach().contiguous(), pads=tuple(pads),
+                         pos=pos.detach().contiguous(), pads=_pads_of(pads, ratio),
                          sigma=None if sigma is None else sigma.detach().contiguous(),
-                         background=background, mask=mask, resample=resample)
+                         background=None if background is None else background.detach().contiguous(),
+                         mask=mask, resample=resample)
         out = torch.empty(prob.K, prob.N, prob.N, device=obj.device)
         ws = _WS.get(prob, 0, chunk)
         B.ptycho_forward([prob], [out], ws)
         ctx.prob = prob
         ctx.chunk = chunk
-        ctx.need = tuple(ctx.needs_input_grad[:3]) + (sigma is not None and ctx.needs_input_grad[3],)
+        ng = ctx.needs_input_grad
+        ctx.need = (ng[0], ng[1], ng[2], sigma is not None and ng[3],
+                    background is not None and ng[4], ratio is not None and ng[5])
+        ctx.ratio_like = None if ratio is None else (ratio.device, ratio.dtype)
         return out
 
     @staticmethod
@@ -136,12 +140,17 @@ class PtychoForwardFn(torch.autograd.Function):
         ws = _WS.get(prob, 1, ctx.chunk)
         B.ptycho_loss_grad([prob], [g], kind=B.LOSS_VJP, eps=0.0, scale=1.0, workspace=ws)
         prob.measured = None
+        gr = g.get("g_ratio")
+        if gr is not None:
+            gr = gr.to(device=ctx.ratio_like[0], dtype=ctx.ratio_like[1])
         return (g.get("g_object"), g.get("g_probe"), g.get("g_pos"), g.get("g_sigma"),
-                None, None, None, None, None)
+                g.get("g_background"), gr, None, None, None, None)
 
 
 def ptycho_forward(obj, probe, pos, pads, sigma=None, background=None, mask=None, resample=None,
-                   chunk: int = 0) -> torch.Tensor:
-    """Predicted patterns I'_k [K][N][N] (differentiable)."""
-    return PtychoForwardFn.apply(obj, probe, pos, sigma, tuple(pads), background, mask, resample,
-                                 int(chunk))
+                   chunk: int = 0, ratio: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Predicted patterns I'_k [K][N][N], differentiable w.r.t. obj, probe,
+    pos, sigma, background and ``ratio`` (exact sampling ratios replacing
+    ``pads``)."""
+    return PtychoForwardFn.apply(obj, probe, pos, sigma, background, ratio, tuple(pads), mask,
+                                 resample, int(chunk))

@@ -185,6 +185,27 @@ def test_forward_autograd_is_the_vjp():
     print("forward VJP", U.compare(got, ref, tol_loss=1e-5))
 
 
+def test_forward_autograd_background_and_distance():
+    # the VJP of the forward model through the background and the exact ratios
+    from paper_2311_14780_amd import autograd as A
+    w = synth.reduced(synth.get_workload("C1"), L=2, M=2, harmonics=(19, 23),
+                      mode_weights=(0.75, 0.25), K=6, name="C1fv")
+    ratios = synth.ratios_for(w.N, w.harmonics, w.ref_harmonic)
+    case = U.make_case(w, pads=ratios, with_bg=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    obj = t(case["obj"]).requires_grad_()
+    bg = t(case["bg"]).requires_grad_()
+    ratio = torch.tensor(ratios, dtype=torch.float64, requires_grad=True)
+    I = A.ptycho_forward(obj, t(case["prb"]), t(case["pos"]), (0, 0), background=bg, ratio=ratio)
+    u = torch.from_numpy(np.random.default_rng(9).normal(size=tuple(I.shape)).astype(np.float32)).to(DEV)
+    (I * u).sum().backward()
+    case["meas"] = u.cpu().numpy()
+    ref = U.oracle_grads(case, kind=3)
+    got = {"loss": float((I.detach() * u).sum().item()), "g_object": obj.grad.cpu().numpy(),
+           "g_background": bg.grad.cpu().numpy(), "g_ratio": ratio.grad.numpy()}
+    print("forward VJP bg/ratio", U.compare(got, ref))
+
+
 def test_c2_full_size_at_bench_configuration():
     """All 400 positions of the four-wavelength workload in one chunk (the
     benchmark's launch configuration); the oracle runs over position blocks
