@@ -260,11 +260,11 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
   if (which != 0) {
     b += align_up(L * plane * sizeof(float2));  // GX
     b += align_up(static_cast<size_t>(n_loss_of(j)) * sizeof(float));
-    b += 2 * align_up(L * (N / col_group_of(j.N)) * sizeof(float));  // dy, sigma
+    b += 2 * align_up(L * adj_part_stride(j.N) * sizeof(float));  // dy, sigma
     b += align_up(L * (N / rows_per_adj_block(j.N)) * sizeof(float));  // dx
     if (any_czt(j)) {  // alpha-derivative terms
       b += align_up(L * (N / rows_per_det_block(j.N)) * sizeof(float));
-      b += align_up(L * (N / col_group_of(j.N)) * sizeof(float));
+      b += align_up(L * adj_part_stride(j.N) * sizeof(float));
     }
   }
   if (has_resample(j)) b += 2 * align_up(plane * sizeof(float));  // ibuf, gbuf
@@ -331,17 +331,14 @@ struct Call {
   std::vector<int> pgroup;  // probe-gradient group size per job
 };
 
-int max_pad(const ptycho_job_t& j) {
-  int m = j.N;
-  for (int l = 0; l < j.L; ++l) m = std::max(m, eff_pad(j, l));
-  return m;
-}
-
 // Positions whose probe-gradient terms are summed in one column-adjoint
 // block (a function of the job alone, so results do not depend on the
 // other jobs of a call).
 int job_probe_group(const ptycho_job_t& j, bool want_probe) {
-  return want_probe ? probe_group_of(j.N, j.M, max_pad(j)) : 1;
+  if (!want_probe) return 1;
+  int g = probe_group_of(j.N, j.M, eff_pad(j, 0));
+  for (int l = 1; l < j.L; ++l) g = std::min(g, probe_group_of(j.N, j.M, eff_pad(j, l)));
+  return g;
 }
 
 // Chunk sizes are multiples of the group size (except a chunk holding the
@@ -537,12 +534,12 @@ void fill_job(Call& c, int i, char** cursor) {
   if (c.which != 0) {
     d.GX = reinterpret_cast<float2*>(take(C * L * plane * sizeof(float2)));
     d.loss_part = reinterpret_cast<float*>(take(C * static_cast<size_t>(n_loss_of(j)) * sizeof(float)));
-    d.dy_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
-    d.sg_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
+    d.dy_part = reinterpret_cast<float*>(take(C * L * adj_part_stride(j.N) * sizeof(float)));
+    d.sg_part = reinterpret_cast<float*>(take(C * L * adj_part_stride(j.N) * sizeof(float)));
     d.dx_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_adj_block(j.N)) * sizeof(float)));
     if (any_czt(j)) {
       d.ra_part = reinterpret_cast<float*>(take(C * L * (N / rows_per_det_block(j.N)) * sizeof(float)));
-      d.rb_part = reinterpret_cast<float*>(take(C * L * (N / col_group_of(j.N)) * sizeof(float)));
+      d.rb_part = reinterpret_cast<float*>(take(C * L * adj_part_stride(j.N) * sizeof(float)));
     }
   }
   if (has_resample(j)) {
@@ -750,7 +747,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         for (int l = 0; l < j.L; ++l) uses |= eff_pad(j, l) == nls[p];
         if (!uses || !cnt[q]) continue;
         grouped |= c.pgroup[members[q]] > 1;
-        lds = std::max(lds, col_adj_lds_of(N, j.M, c.pgroup[members[q]]));
+        lds = std::max(lds, col_adj_lds_of(N, nls[p], j.M, c.pgroup[members[q]]));
       }
       LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
                                         grouped, key.ratio_grad, s));

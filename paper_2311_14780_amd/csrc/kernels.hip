@@ -86,6 +86,20 @@ template <int N> constexpr int rb_row() { return N == 64 ? 32 : (N <= 256 ? 16 :
 template <int N> constexpr int rb_det() { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 template <int N> constexpr int rb_adj() { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 template <int N> constexpr int col_group() { return N <= 256 ? 16 : 8; }
+// Column group of the column adjoint for DFT size nl.  With N = 256 and the
+// sizes listed, 8 columns per block keep the live registers within 128 VGPRs,
+// so two 512-thread blocks share a CU (4 waves per SIMD instead of 2; C2
+// column adjoint 2.86 -> 2.65 ms).  The other instances spill at that bound
+// (exact-ratio length 2N: 3.97 -> 6.9 ms) and keep 16 columns.
+__host__ __device__ constexpr bool adj_narrow(int N, int nl) {
+  return N == 256 && (nl == 256 || nl == 280 || nl == 315 || nl == 343);
+}
+__host__ __device__ constexpr int col_group_adj(int N, int nl) {
+  return adj_narrow(N, nl) ? 8 : (N <= 256 ? 16 : 8);
+}
+// Row stride of the column adjoint's per-block partial sums ([C][L][stride]):
+// the most blocks per column set of any instance of N.
+__host__ __device__ constexpr int adj_stride(int N) { return N <= 128 ? N / 16 : N / 8; }
 
 template <class F, int P, int... Ps>
 __device__ __forceinline__ void pad_switch(int nl, const F& f, IntList<P, Ps...>) {
@@ -129,7 +143,6 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 }
 
 
-__device__ __forceinline__ int col_group_of_dev(int N) { return N <= 256 ? 16 : 8; }
 __device__ __forceinline__ int rb_adj_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 __device__ __forceinline__ int rb_det_dev(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 
@@ -777,8 +790,8 @@ __global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
 // RATIO: the exact-ratio instance that also computes the y-axis terms of
 // dL/d alpha (launches whose jobs want them).
 template <int N, int NL, bool GROUPED, bool RATIO>
-__global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
-  constexpr int G = col_group<N>();
+__global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Launch la) {
+  constexpr int G = col_group_adj(N, NL);
   const UnitRef r = decode<N / G>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
@@ -927,13 +940,13 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   {
     const float s = block_sum<CNT>(sgsum, red);
     if (tid == 0)
-      gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s;
+      gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] = s;
   }
   if (want_ratio) {
     const double a = jb.czt_alpha[l];
     const float s = block_sum<CNT>(rsum, red);
     if (tid == 0)
-      gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] =
+      gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] =
           static_cast<float>(2.0 * kPi / (a * a)) * s;
   }
   // Ghat = FFT_y(G_Osh): y-position derivative and adjoint y-shift
@@ -960,7 +973,7 @@ __global__ __launch_bounds__(CNT) void k_col_adj(Launch la) {
   fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_gx);
   const float s = block_sum<CNT>(dsum, red);
   if (tid == 0)
-    gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * (N / G) + r.sub] = s * invN;
+    gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] = s * invN;
   }  // positions of the group
   if (group_acc && cbeg < cend) {
     gf2* __restrict__ Zg = gmem(jb.Y) + (static_cast<size_t>(cbeg) * jb.L + l) * jb.M * N * N + x0;
@@ -1160,7 +1173,9 @@ __global__ void k_finalize_chunk(Launch la) {
   const int C = min(jb.C, jb.K - la.iter * jb.C);
   if (c >= C) return;
   const int k = la.iter * jb.C + c;
-  const int n_dy = jb.N / col_group_of_dev(jb.N), n_dx = jb.N / rb_adj_dev(jb.N);
+  // column-adjoint partials: n_dy(l) per slot, row stride sdy
+  const int sdy = adj_stride(jb.N), n_dx = jb.N / rb_adj_dev(jb.N);
+  auto n_dy = [&](int l) { return jb.N / col_group_adj(jb.N, jb.pad[l]); };
   double ls = 0.0;
   const gf32* lp = gmem(jb.loss_part);
   for (int i = 0; i < jb.n_loss; ++i) ls += lp[static_cast<size_t>(c) * jb.n_loss + i];
@@ -1168,9 +1183,9 @@ __global__ void k_finalize_chunk(Launch la) {
   if (!jb.want_adjoint) return;
   float gy = 0.f, gx = 0.f, gs = 0.f;
   for (int l = 0; l < jb.L; ++l) {
-    for (int i = 0; i < n_dy; ++i) {
-      gy += gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
-      gs += gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+    for (int i = 0; i < n_dy(l); ++i) {
+      gy += gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
+      gs += gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
     }
     for (int i = 0; i < n_dx; ++i) gx += gmem(jb.dx_part)[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
   }
@@ -1186,7 +1201,7 @@ __global__ void k_finalize_chunk(Launch la) {
       for (int l = w * jb.Ns; l < (w + 1) * jb.Ns; ++l) {  // slots of wavelength w
         if (!jb.czt[l]) continue;
         for (int i = 0; i < n_ra; ++i) da += gmem(jb.ra_part)[(static_cast<size_t>(c) * jb.L + l) * n_ra + i];
-        for (int i = 0; i < n_dy; ++i) da += gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * n_dy + i];
+        for (int i = 0; i < n_dy(l); ++i) da += gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
       }
       gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.Lw + w] = da;
     }
@@ -1377,23 +1392,23 @@ int czt_table_blocks(int N) { return (2 * N + NT - 1) / NT + (2 * N + NT - 1) / 
 int rows_per_det_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 int rows_per_adj_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 int rows_per_row_block(int N) { return N == 64 ? 32 : (N <= 256 ? 16 : 8); }
-int col_group_of(int N) { return N <= 256 ? 16 : 8; }
+int adj_part_stride(int N) { return adj_stride(N); }
 
 constexpr int kProbeGroup = 4;
 // LDS a column-adjoint block may use (gfx950: 160 KB per workgroup), less a
 // margin for the reduction scratch.
 constexpr size_t kColAdjLds = 156 * 1024;
 
-int probe_group_of(int N, int M, int nl_max) {
-  const size_t G = static_cast<size_t>(col_group_of(N));
+int probe_group_of(int N, int M, int nl) {
+  const size_t G = static_cast<size_t>(col_group_adj(N, nl));
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
-  const size_t buf = static_cast<size_t>(nl_max) * (G + 1) * sizeof(float2);
+  const size_t buf = static_cast<size_t>(nl) * (G + 1) * sizeof(float2);
   return acc + buf <= kColAdjLds ? kProbeGroup : 1;
 }
 
-size_t col_adj_lds_of(int N, int M, int group) {
+size_t col_adj_lds_of(int N, int nl, int M, int group) {
   if (group <= 1) return 0;
-  return static_cast<size_t>(M) * N * col_group_of(N) * sizeof(float2);
+  return static_cast<size_t>(M) * N * col_group_adj(N, nl) * sizeof(float2);
 }
 
 hipError_t launch_write_table(int* dst, const int* data, int n, hipStream_t s) {
@@ -1523,7 +1538,7 @@ hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size
     constexpr int NN = decltype(nc)::value;
     return host_pad(nl, [&](auto pc) {
       constexpr int NL = decltype(pc)::value;
-      const dim3 g = grid1(units * (NN / col_group<NN>()));
+      const dim3 g = grid1(units * (NN / col_group_adj(NN, NL)));
       if constexpr (NL == czt_nb<NN>()) {
         if (ratio) return launch_col_adj_inst<NN, NL, true>(g, la, dyn_lds, grouped, s);
       }

@@ -143,13 +143,16 @@ int czt_len(int N);
 int rows_per_det_block(int N);
 int rows_per_adj_block(int N);
 int rows_per_row_block(int N);
-int col_group_of(int N);
-// Positions per probe-gradient group for a job (depends only on the job):
-// the column adjoint keeps an M x N x G accumulator in LDS when it fits.
-int probe_group_of(int N, int M, int nl_max);
-// Dynamic LDS bytes of the column adjoint for a job with M modes (0 if the
-// job's group is 1).
-size_t col_adj_lds_of(int N, int M, int group);
+// Row stride of the column adjoint's per-block partial sums (dy, sigma and
+// alpha parts are [C][L][stride]).
+int adj_part_stride(int N);
+// Positions per probe-gradient group that the column-adjoint instance of DFT
+// size nl allows for a job with M modes: it keeps an M x N x G accumulator in
+// LDS when that fits.  A job's group is the least over its slots' sizes.
+int probe_group_of(int N, int M, int nl);
+// Dynamic LDS bytes of the column-adjoint instance of DFT size nl for a job
+// with M modes (0 if the job's group is 1).
+size_t col_adj_lds_of(int N, int nl, int M, int group);
 
 // Launchers (asynchronous on `s`).  `units` is the total number of work
 // units of the launch's segments.
