@@ -185,12 +185,14 @@ __device__ __forceinline__ UnitRef decode(const Launch& la, int b = -1) {
 // Copies a table carried in the launch's own argument block to device
 // memory: the payload is the first kernel argument, so it starts at the
 // kernel-argument segment pointer.
-// decode() for the column kernels.  Workgroups are dealt to the 8 XCDs in
-// turn (block b to XCD b mod 8), and each XCD has its own L2.  Renumbering
-// the blocks so that each XCD receives one contiguous run of block indices
-// keeps the neighbouring column groups of a plane, whose 64-byte column
-// segments share 128-byte lines, in the same L2 (column adjoint with 8-column
-// groups: C2 2.65 -> 2.37 ms, C3 216 -> 178 ms; column forward, C3: 105 -> 95 ms).
+// decode() for the column and detector kernels.  Workgroups are dealt to the
+// 8 XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2.
+// Renumbering the blocks so that each XCD receives one contiguous run of block
+// indices keeps the neighbouring column groups of a plane, whose 64-byte
+// column segments share 128-byte lines, in the same L2 (column adjoint with
+// 8-column groups: C2 2.65 -> 2.37 ms, C3 216 -> 178 ms; column forward, C3:
+// 105 -> 95 ms), and the row blocks of one position together (detector, C3:
+// 188 -> 181 ms).
 template <int GX>
 __device__ __forceinline__ UnitRef decode_xcd(const Launch& la) {
   const int n = gridDim.x, b = blockIdx.x;
@@ -591,7 +593,7 @@ template <int N, int MODE, int VAR>
 __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill) {
   constexpr int RB = rb_det<N>();
   using Rows = DetList<N, (VAR >= 1)>;
-  const UnitRef r = decode<N / RB>(la);
+  const UnitRef r = decode_xcd<N / RB>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   constexpr int LPMAX = max_row_lp(Rows{});
