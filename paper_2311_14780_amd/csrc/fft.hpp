@@ -60,6 +60,13 @@ __device__ __forceinline__ void stv(float2* p, int i, float2 v) { p[i] = v; }
 __device__ __forceinline__ void stv(lf2* p, int i, float2 v) { p[i] = vf2{v.x, v.y}; }
 template <class I>
 __device__ __forceinline__ void stv(gf2* p, I i, float2 v) { p[i] = vf2{v.x, v.y}; }
+// Streaming store (nontemporal): for planes written once and read by a later
+// kernel, in runs of whole 128-byte lines.  Partial lines written this way are
+// not merged in L2 (64-byte column segments got slower).
+template <class I>
+__device__ __forceinline__ void stv_nt(gf2* p, I i, float2 v) {
+  __builtin_nontemporal_store(vf2{v.x, v.y}, p + i);
+}
 
 // ----------------------------------------------------------- complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
