@@ -293,7 +293,8 @@ PTYCHO_PLAN(168, 7, 3, 8)
 PTYCHO_PLAN(189, 7, 3, 9)
 // 256: three passes (32, 32 and 64 butterflies per line) rather than 16 x 16,
 // whose 16 butterflies per line left half the threads of a 16-line, 512-thread
-// column block idle (C2 step 8.13 -> 8.03 ms)
+// column block idle (loss + gradient step of 400 positions x 4 wavelengths x
+// 3 modes at N = 256: 8.13 -> 8.03 ms)
 PTYCHO_PLAN(256, 8, 8, 4)
 PTYCHO_PLAN(280, 7, 5, 8)
 PTYCHO_PLAN(300, 5, 5, 12)

@@ -88,9 +88,10 @@ template <int N> constexpr int rb_adj() { return N <= 128 ? 16 : (N == 512 ? 4 :
 template <int N> constexpr int col_group() { return N <= 256 ? 16 : 8; }
 // Column group of the column adjoint for DFT size nl.  With N = 256 and the
 // sizes listed, 8 columns per block keep the live registers within 128 VGPRs,
-// so two 512-thread blocks share a CU (4 waves per SIMD instead of 2; C2
-// column adjoint 2.86 -> 2.65 ms).  The other instances spill at that bound
-// (exact-ratio length 2N: 3.97 -> 6.9 ms) and keep 16 columns.
+// so two 512-thread blocks share a CU (4 waves per SIMD instead of 2; column
+// adjoint of 400 positions x 4 wavelengths x 3 modes at N = 256: 2.86 -> 2.65
+// ms per step).  The other instances spill at that bound (exact-ratio length
+// 2N: 3.97 -> 6.9 ms) and keep 16 columns.
 __host__ __device__ constexpr bool adj_narrow(int N, int nl) {
   return N == 256 && (nl == 256 || nl == 280 || nl == 315 || nl == 343);
 }
@@ -189,10 +190,11 @@ __device__ __forceinline__ UnitRef decode(const Launch& la, int b = -1) {
 // 8 XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2.
 // Renumbering the blocks so that each XCD receives one contiguous run of block
 // indices keeps the neighbouring column groups of a plane, whose 64-byte
-// column segments share 128-byte lines, in the same L2 (column adjoint with
-// 8-column groups: C2 2.65 -> 2.37 ms, C3 216 -> 178 ms; column forward, C3:
-// 105 -> 95 ms), and the row blocks of one position together (detector, C3:
-// 188 -> 181 ms).
+// column segments share 128-byte lines, in the same L2, and the row blocks of
+// one position together.  Per step, N = 256 (400 positions, 4 wavelengths x 3
+// modes): column adjoint 2.65 -> 2.37 ms; N = 512 (2500 positions, 5 x 8):
+// column adjoint 216 -> 178 ms, column forward 105 -> 95 ms, detector
+// 188 -> 181 ms.
 template <int GX>
 __device__ __forceinline__ UnitRef decode_xcd(const Launch& la) {
   const int n = gridDim.x, b = blockIdx.x;
@@ -351,7 +353,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   gf2* __restrict__ X = gmem(jb.X) + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
   constexpr float inv = 1.0f / N;
   auto ld_buf = [&](int line, int i) { return buf[Ix::at(line, i)]; };
-  // streaming stores of whole rows (C2 row forward 0.266 -> 0.225 ms, C5 1.02 -> 0.87 ms)
+  // streaming stores of whole rows (row forward, 400 positions x 4 wavelengths
+  // at N = 256: 0.266 -> 0.225 ms; 900 x 3 at N = 384: 1.02 -> 0.87 ms)
   auto st_x = [&](int line, int i, float2 v) { stv_nt(X, line * N + i, cscale(v, inv)); };
   fft_lines<N, true, RB, NT, LP, false>(buf, tw, ld_buf, st_x);
 }
@@ -428,8 +431,9 @@ __global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
         if (u >= NL) u -= NL;
         if (u < N) {
           // 16-column groups write whole 128-byte lines: streaming stores
-          // (C2 column forward 1.20 -> 1.14 ms); 8-column groups keep
-          // ordinary stores, whose line halves L2 merges
+          // (400 positions x 4 wavelengths x 3 modes at N = 256: 1.20 ->
+          // 1.14 ms per step); 8-column groups keep ordinary stores, whose
+          // line halves L2 merges
           if constexpr (G == 16) stv_nt(Y, u * N + line, cscale(v, ps));
           else stv(Y, u * N + line, cscale(v, ps));
         }
