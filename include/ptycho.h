@@ -238,6 +238,11 @@ int32_t ptycho_transpose_table(const int32_t* idx, const float* w, int32_t n_out
 int32_t ptycho_profile(int32_t enable);
 int32_t ptycho_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches);
 const char* ptycho_kernel_class_name(int32_t kernel_class);
+/* Restricts the bracketing to the kernel classes whose bit (1 << kernel_class)
+   is set in class_mask, for launches enqueued after the call (all classes by
+   default and after ptycho_profile(0)); fewer events per call perturb the
+   timed launches less.  Always returns PTYCHO_OK. */
+int32_t ptycho_profile_classes(uint32_t class_mask);
 
 /* Static description of an error code. */
 const char* ptycho_error_string(int32_t code);

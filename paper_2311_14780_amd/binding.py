@@ -119,6 +119,8 @@ def lib():
         L.ptycho_profile_read.argtypes = [_c_i32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]
         L.ptycho_profile_read.restype = _c_i32
+        L.ptycho_profile_classes.argtypes = [ctypes.c_uint32]
+        L.ptycho_profile_classes.restype = _c_i32
         L.ptycho_kernel_class_name.argtypes = [_c_i32]
         L.ptycho_kernel_class_name.restype = ctypes.c_char_p
         _lib = L
@@ -341,6 +343,26 @@ def ptycho_profile(enable: bool) -> None:
     code = lib().ptycho_profile(1 if enable else 0)
     if code:
         raise PtychoError(code, "ptycho_profile")
+
+
+def ptycho_profile_classes(names) -> None:
+    """Brackets only the named kernel classes (None: all) while profiling."""
+    mask = 0xFFFFFFFF
+    if names is not None:
+        index = {}
+        i = 0
+        while True:
+            n = lib().ptycho_kernel_class_name(i)
+            if n is None:
+                break
+            index[n.decode()] = i
+            i += 1
+        mask = 0
+        for n in names:
+            mask |= 1 << index[n]
+    code = lib().ptycho_profile_classes(mask)
+    if code:
+        raise PtychoError(code, "ptycho_profile_classes")
 
 
 def ptycho_profile_read() -> dict:

@@ -119,6 +119,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mutex;
 bool g_prof_on = false;
+uint32_t g_prof_mask = ~0u;  // kernel classes bracketed while profiling is on
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
 double g_prof_ms[KC_COUNT];
@@ -156,7 +157,7 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   ProfScope(int c, hipStream_t st) : cls(c), s(st) {
     std::lock_guard<std::mutex> lock(g_prof_mutex);
-    if (!g_prof_on) return;
+    if (!g_prof_on || !((g_prof_mask >> cls) & 1u)) return;
     a = prof_event();
     if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
   }
@@ -1028,6 +1029,13 @@ int32_t ptycho_profile(int32_t enable) {
     }
   }
   g_prof_on = enable != 0;
+  if (!g_prof_on) g_prof_mask = ~0u;
+  return PTYCHO_OK;
+}
+
+int32_t ptycho_profile_classes(uint32_t class_mask) {
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  g_prof_mask = class_mask;
   return PTYCHO_OK;
 }
 
