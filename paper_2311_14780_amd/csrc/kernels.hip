@@ -1222,6 +1222,24 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
 }
 
 // ---------------------------------------------------------------- finalize
+// s + p[0] + p[stride] + ... + p[(n - 1) stride], added left to right in the
+// accumulator's type, with eight loads in flight before their additions
+// (the single-thread sums were bound by one load latency per term).
+template <class A, class T>
+__device__ __forceinline__ A ordered_sum(A s, const PTYCHO_GLOBAL T* p, long long n,
+                                         long long stride = 1) {
+  long long i = 0;
+  for (; i + 8 <= n; i += 8) {
+    T v[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) v[h] = p[(i + h) * stride];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) s += v[h];
+  }
+  for (; i < n; ++i) s += p[i * stride];
+  return s;
+}
+
 // Ordered per-position sums of the partials.  units: blocks of 64 positions
 __global__ void k_finalize_chunk(Launch la) {
   const UnitRef r = decode<1>(la);
@@ -1234,18 +1252,16 @@ __global__ void k_finalize_chunk(Launch la) {
   // column-adjoint partials: n_dy(l) per slot, row stride sdy
   const int sdy = adj_stride(jb.N), n_dx = jb.N / rb_adj_dev(jb.N);
   auto n_dy = [&](int l) { return jb.N / col_group_adj(jb.N, jb.pad[l]); };
-  double ls = 0.0;
-  const gf32* lp = gmem(jb.loss_part);
-  for (int i = 0; i < jb.n_loss; ++i) ls += lp[static_cast<size_t>(c) * jb.n_loss + i];
+  const double ls =
+      ordered_sum(0.0, gmem(jb.loss_part) + static_cast<size_t>(c) * jb.n_loss, jb.n_loss);
   gmem(jb.loss_k)[k] = ls;
   if (!jb.want_adjoint) return;
   float gy = 0.f, gx = 0.f, gs = 0.f;
   for (int l = 0; l < jb.L; ++l) {
-    for (int i = 0; i < n_dy(l); ++i) {
-      gy += gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
-      gs += gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
-    }
-    for (int i = 0; i < n_dx; ++i) gx += gmem(jb.dx_part)[(static_cast<size_t>(c) * jb.L + l) * n_dx + i];
+    const size_t row = static_cast<size_t>(c) * jb.L + l;
+    gy = ordered_sum(gy, gmem(jb.dy_part) + row * sdy, n_dy(l));
+    gs = ordered_sum(gs, gmem(jb.sg_part) + row * sdy, n_dy(l));
+    gx = ordered_sum(gx, gmem(jb.dx_part) + row * n_dx, n_dx);
   }
   if (jb.g_pos) {
     gmem(jb.g_pos)[2 * k] = gy;
@@ -1258,8 +1274,9 @@ __global__ void k_finalize_chunk(Launch la) {
       double da = 0.0;
       for (int l = w * jb.Ns; l < (w + 1) * jb.Ns; ++l) {  // slots of wavelength w
         if (!jb.czt[l]) continue;
-        for (int i = 0; i < n_ra; ++i) da += gmem(jb.ra_part)[(static_cast<size_t>(c) * jb.L + l) * n_ra + i];
-        for (int i = 0; i < n_dy(l); ++i) da += gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * sdy + i];
+        const size_t row = static_cast<size_t>(c) * jb.L + l;
+        da = ordered_sum(da, gmem(jb.ra_part) + row * n_ra, n_ra);
+        da = ordered_sum(da, gmem(jb.rb_part) + row * sdy, n_dy(l));
       }
       gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.Lw + w] = da;
     }
@@ -1332,24 +1349,19 @@ __global__ void k_loss_total(Launch la, LossDev loss, float scale) {
     return;
   }
   if (jb.loss) {
-    double s = 0.0;
-    const PTYCHO_GLOBAL double* lk = gmem(jb.loss_k);
-    for (int k = 0; k < jb.K; ++k) s += lk[k];
+    double s = ordered_sum(0.0, gmem(jb.loss_k), jb.K);
     s *= scale;
     if (loss.l1 != 0.f || loss.tv != 0.f) {  // the regulariser, added unscaled
       const size_t n = static_cast<size_t>(jb.L) *
                        ((static_cast<size_t>(jb.H) * jb.W + kRegBlock - 1) / kRegBlock);
-      double rs = 0.0;
-      for (size_t i = 0; i < n; ++i) rs += gmem(jb.reg_part)[i];
-      s += rs;
+      s += ordered_sum(0.0, gmem(jb.reg_part), static_cast<long long>(n));
     }
     *gmem(jb.loss) = static_cast<float>(s);
   }
   if (jb.g_ratio) {
     // dL/d alpha_l: ordered sum over positions (the terms carry the scale)
     for (int w = 0; w < jb.Lw; ++w) {
-      double s = 0.0;
-      for (int k = 0; k < jb.K; ++k) s += gmem(jb.ratio_k)[static_cast<size_t>(k) * jb.Lw + w];
+      const double s = ordered_sum(0.0, gmem(jb.ratio_k) + w, jb.K, jb.Lw);
       gmem(jb.g_ratio)[w] = static_cast<float>(s);
     }
   }
