@@ -254,3 +254,13 @@ def test_invalid_loss_parameters_rejected_on_host(fields):
     rc = B.lib().ptycho_loss_grad(ctypes.byref(j), 1, ctypes.byref(loss), ctypes.byref(grads),
                                   ctypes.c_void_p(0x2000), 1 << 20, None)
     assert rc == B.PTYCHO_EINVAL
+
+
+def test_profile_class_selection_on_the_host():
+    # the class mask is host state: set and cleared without launching anything
+    B.ptycho_profile_classes(["det", "col_adj"])
+    B.ptycho_profile_classes(None)
+    with pytest.raises(KeyError):
+        B.ptycho_profile_classes(["no_such_class"])
+    assert B.lib().ptycho_profile_classes(0) == 0
+    B.ptycho_profile(False)  # also resets the mask to every class
