@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of the ptychography loss + gradient iteration on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload C2]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload C3] [--extra C2]
 
 One step is one pass of the whole hot path over the workload: positions ->
 object patches -> sub-pixel Fourier shift -> probe modes -> per-wavelength
@@ -11,15 +11,22 @@ probe and positions (``ptycho_step``).  All inputs are seeded synthetic data
 resident in HBM before the timed region starts; the measured patterns are
 Poisson draws from the model's own forward pass of the ground truth.
 
-Prints one JSON line.  ``value`` is pattern-modes per second (one pattern-mode
-is one (position, wavelength, probe mode) propagation, forward and adjoint).
+Prints one JSON line.  The headline workload is the largest single-GPU
+configuration (C3: 5 wavelengths x 8 probe modes, 512 x 512 probe, 3072 x 3072
+object per wavelength, 2500 positions); ``extra`` holds the same figures for
+the four-wavelength 256 x 256 workload (C2).  ``value`` is pattern-modes per
+second (one pattern-mode is one (position, wavelength, probe mode)
+propagation, forward and adjoint).
 ``roofline`` reports the kernel class with the largest GPU time: algorithmic
 HBM bytes per launch / average launch duration (HIP events on the launch
 stream, over the timed region) against the 8 TB/s HBM3E peak.
 ``roofline.traffic`` is the measured HBM traffic per launch of that kernel
 (rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain-copy
 calibration; committed under profiles/), reported only while the kernel
-sources are the ones that were measured, else null.
+sources are the ones that were measured, else null.  ``roofline.valu_issue_frac``
+is the same kernel's VALU issue rate against the chip's (SQ_INSTS_VALU per
+launch from a committed counter pass / launch duration, against 1024 SIMDs x
+clock / 4 cycles per wave64 instruction), under the same source condition.
 ``cpu_baseline`` times the FP64 oracle on a bounded sample of positions.
 ``serving`` runs a reduced serving stream (continuous batching against
 first-come first-served sequential execution); ``--serving-jobs 64
@@ -75,22 +82,54 @@ def step_alg_bytes(K, L, M, N, H, W) -> float:
                ("row_fwd", "col_fwd", "det", "col_adj", "row_adj", "obj_gather", "probe_reduce", "adam"))
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch from the committed counter summary, if the kernel
-    sources still hash to the measured ones; else None."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_step_hbm_traffic.json")
-    if not os.path.exists(path):
-        return None
-    d = json.load(open(path))
+def kernel_source_sha256() -> str:
     csrc = os.path.join(ROOT, "paper_2311_14780_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read()
                    for f in ("kernels.hip", "fft.hpp", "kernels.hpp"))
-    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+    return hashlib.sha256(src).hexdigest()
+
+
+def _profile_entry(workload: str, kind: str, kernel: str):
+    """Per-launch figures of a kernel class from a committed counter summary
+    (profiles/<workload>_step_<kind>.json), if the kernel sources still hash
+    to the measured ones; else None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_step_{kind}.json")
+    if not os.path.exists(path):
         return None
-    k = d["kernels"].get(kernel)
+    d = json.load(open(path))
+    if kernel_source_sha256() != d.get("source_sha256"):
+        return None
+    return d["kernels"].get(kernel)
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE passes), or None."""
+    k = _profile_entry(workload, "hbm_traffic", kernel)
     if not k:
         return None
     return float(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
+
+
+# VALU issue limit: 256 CUs x 4 SIMDs issue one wave64 VALU instruction each
+# per 4 cycles (16 lanes per SIMD; packed FP32 is not used).
+SIMDS = 1024
+CYCLES_PER_WAVE64_VALU = 4
+
+
+def valu_issue(workload: str, kernel: str, avg_launch_us: float):
+    """VALU issue fraction of a kernel class: SQ_INSTS_VALU per launch (a
+    committed counter pass) / (1024 SIMDs x clock / 4 x launch duration),
+    with the clock measured in the same pass (GRBM_GUI_ACTIVE per XCD over
+    the kernel's duration); None without a summary for these sources."""
+    k = _profile_entry(workload, "valu_counters", kernel)
+    if not k:
+        return None
+    clk = float(k["clock_hz"])
+    peak = SIMDS * clk / CYCLES_PER_WAVE64_VALU  # wave64 VALU instructions per second
+    insts = float(k["sq_insts_valu_per_launch"])
+    return dict(valu_insts_per_launch=insts, clock_GHz=round(clk / 1e9, 3),
+                issue_rate=round(insts / (avg_launch_us * 1e-6), 1), peak_rate=round(peak, 1),
+                frac=round(insts / (avg_launch_us * 1e-6) / peak, 4))
 
 
 def build_inputs(w, device, exact_ratio: bool = False):
@@ -235,35 +274,37 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * mib * 2**20 / sec / 1e9
 
 
-def cpu_baseline(w, truth, start, budget_s: float = 12.0, max_positions: int = 256):
-    """FP64 oracle loss + gradient on the first positions of the workload,
-    one position at a time until the time budget is spent."""
+def cpu_baseline(w, truth, start, budget_s: float = 20.0, max_positions: int = 256):
+    """FP64 oracle loss + gradient of the workload's first positions, one
+    position at a time until the time budget is spent (at least two).  Each
+    position's measured pattern is drawn from the oracle's forward model of
+    the truth before its timed call; only the loss + gradient is timed."""
     import oracle
     import synth
     obj = start["object"].astype(np.complex64).astype(np.complex128)
     prb = start["probe"].astype(np.complex64).astype(np.complex128)
-    n_pre = max_positions
-    I = oracle.forward(truth["object"], truth["probe"], truth["pos"][:n_pre], truth["pads"],
-                       resample_table=truth["resample"])
-    meas = synth.sample_counts(I, w.seed)
     exact = any(oracle.is_ratio(p) for p in start["pads"])
     elapsed, done = 0.0, 0
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):  # one core: the matrix products of the exact ratio too
-        while done < n_pre and (elapsed < budget_s or done < 2):
+        while done < min(max_positions, w.K) and (elapsed < budget_s or done < 2):
+            k = done
+            I = oracle.forward(truth["object"], truth["probe"], truth["pos"][k:k + 1],
+                               truth["pads"], resample_table=truth["resample"])
+            meas = synth.sample_counts(I, w.seed + k)
             t0 = time.perf_counter()
-            oracle.loss_grad(obj, prb, start["pos"][:n_pre], start["pads"], meas,
-                             mask=truth["mask"], resample_table=truth["resample"], positions=[done])
+            oracle.loss_grad(obj, prb, start["pos"][k:k + 1], start["pads"], meas,
+                             mask=truth["mask"], resample_table=truth["resample"])
             elapsed += time.perf_counter() - t0
             done += 1
     pm = done * w.L * w.M * w.Ns
     prop = ("exact-ratio scaled DFT as matrix products" if exact
             else "zero-padded DFT by pocketfft")
     return dict(value=pm / elapsed, unit="pattern-modes/s", cores=1, kind="oracle",
-                sample=(f"{done} of {w.K} positions of {w.name} at full N/L/M, amplitude loss + "
-                        f"object/probe/position/sigma gradients, FP64 NumPy ({prop}), one "
-                        f"thread, {elapsed:.1f} s; host has {os.cpu_count()} logical CPUs, "
-                        f"{cpu_model()}"))
+                sample=(f"{done} of {w.K} positions of {w.name} at full N/L/M "
+                        f"({pm} pattern-modes), amplitude loss + object/probe/position/sigma "
+                        f"gradients, FP64 NumPy ({prop}), one thread, {elapsed:.1f} s; host has "
+                        f"{os.cpu_count()} logical CPUs, {cpu_model()}"))
 
 
 def copy_calibration(mib: int) -> int:
@@ -281,12 +322,145 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def time_workload(B, w, dev, args, czt: bool, label: str) -> dict:
+    """Times ``args.steps`` fused steps (loss + gradients + Adam) of workload
+    ``w`` after ``args.warmup`` warm-up steps; returns the figures of the
+    JSON line (value, ms per step, step and dominant-kernel rooflines,
+    per-class kernel times) and the inputs (for the CPU baseline)."""
+    import torch
+    print(f"[{label}] building inputs of {w.name}", file=sys.stderr, flush=True)
+    truth, start, prob = build_inputs(w, dev, exact_ratio=czt)
+    K, L, M, N, H, W = w.K, w.L, w.M, w.N, w.H, w.W
+    g = dict(loss=torch.zeros(1, device=dev), g_object=torch.zeros_like(prob.object),
+             g_probe=torch.zeros_like(prob.probe), g_pos=torch.zeros(K, 2, device=dev),
+             g_sigma=torch.zeros(K, device=dev))
+    zeros = lambda x: torch.zeros(x.numel() * (2 if x.is_complex() else 1), device=dev)
+    adam = dict(m_object=zeros(prob.object), v_object=zeros(prob.object),
+                m_probe=zeros(prob.probe), v_probe=zeros(prob.probe),
+                m_pos=zeros(prob.pos), v_pos=zeros(prob.pos),
+                lr_object=1e-3, lr_probe=1e-3, lr_pos=5e-3, t=0)
+    ws = B.workspace([prob], 2)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        adam["t"] += 1
+        B.ptycho_step([prob], [g], [adam], kind=B.LOSS_AMPLITUDE, eps=1e-6, scale=1.0,
+                      workspace=ws, stream=stream)
+
+    # Kernel timing: with two or more warm-up steps, every launch of the
+    # warm-up steps after the first is bracketed with HIP events (the
+    # per-class breakdown), and in the timed region only the launches of the
+    # class with the most time, whose figures the roofline object reports.
+    # With fewer warm-up steps every launch of the timed region is bracketed.
+    timing = not args.no_kernel_timing
+    split = timing and args.warmup >= 2
+    kern_warm, n_warm = {}, 0
+    print(f"[{label}] {args.warmup} warm-up steps", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        if split and i == 1:
+            torch.cuda.synchronize()
+            B.ptycho_profile(True)
+        step()
+    torch.cuda.synchronize()
+    if split:
+        kern_warm, n_warm = B.ptycho_profile_read(), args.warmup - 1
+        B.ptycho_profile(False)
+    dom_warm = max(kern_warm, key=lambda k: kern_warm[k][0]) if kern_warm else None
+    if timing:
+        B.ptycho_profile(True)
+        if dom_warm is not None:
+            B.ptycho_profile_classes([dom_warm])
+    print(f"[{label}] {args.steps} timed steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if timing:
+        kern = B.ptycho_profile_read()
+        B.ptycho_profile(False)
+    status = B.ptycho_status(ws, 0)
+    if status != 0:
+        raise RuntimeError(f"device status {status}: a window left the object")
+    ms = (t1 - t0) * 1e3 / args.steps
+    pm = K * L * M * w.Ns
+    value = pm / (ms * 1e-3)
+    b_step = step_alg_bytes(K, L, M, N, H, W)
+
+    roof = None
+    kern_out = {}
+    if kern:
+        # per-class figures: the timed region's where it bracketed the class,
+        # else those of the profiled warm-up steps
+        for src, nsteps in ((kern_warm, n_warm), (kern, args.steps)):
+            for name, (tot, n) in src.items():
+                if n:
+                    kern_out[name] = dict(ms_per_step=tot / nsteps, launches_per_step=n / nsteps,
+                                          avg_launch_us=1e3 * tot / n,
+                                          timed_region=src is kern)
+        dom = dom_warm or max(kern_out, key=lambda k: kern_out[k]["ms_per_step"])
+        d = kern_out[dom]
+        per_launch = alg_bytes(dom, K, L, M, N, H, W) / d["launches_per_step"]
+        achieved = per_launch / (d["avg_launch_us"] * 1e-6) / 1e9
+        traffic = None if czt else measured_traffic(w.name, dom)
+        roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic / 1e9, 4),
+                    traffic_unit="GB per launch",
+                    alg_bytes_per_launch=per_launch, avg_launch_us=round(d["avg_launch_us"], 2))
+        vi = None if czt else valu_issue(w.name, dom, d["avg_launch_us"])
+        roof["valu_issue_frac"] = None if vi is None else vi["frac"]
+        roof["valu_issue"] = vi
+        for name, d in kern_out.items():
+            b = alg_bytes(name, K, L, M, N, H, W)
+            if b:
+                d["alg_GBps"] = round(b / (d["ms_per_step"] * 1e-3) / 1e9, 1)
+            if not czt:
+                v = valu_issue(w.name, name, d["avg_launch_us"])
+                if v is not None:
+                    d["valu_issue_frac"] = v["frac"]
+    graph = None
+    if args.graph:
+        graph = graph_timing(B, prob, g, ws, args.steps, args.warmup)
+    pads = [round(p, 4) if isinstance(p, float) else int(p) for p in prob.pads]
+    prop = ("exact-ratio propagator (scaled DFT by Bluestein's method, FFT length 2N), ratios "
+            if czt else "zero-padded DFT, pads ")
+    del g, adam, ws, prob
+    torch.cuda.empty_cache()
+    print(f"[{label}] {w.name}: {ms:.3f} ms per step", file=sys.stderr, flush=True)
+    return dict(
+        value=round(value, 1), ms_per_step=round(ms, 4),
+        config={"workload": (f"{w.name}: {L} wavelengths (harmonics {'/'.join(map(str, w.harmonics))}) "
+                             f"x {M} probe modes, probe {N}x{N}, object {H}x{W} per wavelength, "
+                             f"{K} positions ({w.scan}), {prop}{'/'.join(map(str, pads))}, "
+                             f"{w.photons:.0e} photons/pattern; step = loss + gradients + Adam"),
+                "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": pads,
+                "propagator": "exact-ratio" if czt else "zero-padded DFT",
+                "parallelism": "single GPU"},
+        step_roofline={"alg_bytes_per_step": b_step,
+                       "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        roofline=roof, graph=graph, kernels=kern_out,
+        kernel_timing=(None if not timing else
+                       "HIP events around the dominant class's launches in the timed region; "
+                       "other classes from the bracketed warm-up steps" if split else
+                       "HIP events around every launch of the timed region"),
+        _truth=truth, _start=start)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="C3",
+                    help="workload of the headline line (default C3, the largest "
+                         "single-GPU configuration)")
+    ap.add_argument("--extra", default="C2",
+                    help="comma-separated workloads also timed and reported under 'extra' "
+                         "(default C2; empty for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -326,135 +500,44 @@ def main(argv=None):
     import synth
     from paper_2311_14780_amd import binding as B
 
-    w = synth.get_workload(args.workload)
     dev = torch.device("cuda:0")
     czt = args.propagator == "czt"
-    truth, start, prob = build_inputs(w, dev, exact_ratio=czt)
-    K, L, M, N, H, W = w.K, w.L, w.M, w.N, w.H, w.W
-    g = dict(loss=torch.zeros(1, device=dev), g_object=torch.zeros_like(prob.object),
-             g_probe=torch.zeros_like(prob.probe), g_pos=torch.zeros(K, 2, device=dev),
-             g_sigma=torch.zeros(K, device=dev))
-    zeros = lambda x: torch.zeros(x.numel() * (2 if x.is_complex() else 1), device=dev)
-    adam = dict(m_object=zeros(prob.object), v_object=zeros(prob.object),
-                m_probe=zeros(prob.probe), v_probe=zeros(prob.probe),
-                m_pos=zeros(prob.pos), v_pos=zeros(prob.pos),
-                lr_object=1e-3, lr_probe=1e-3, lr_pos=5e-3, t=0)
-    ws = B.workspace([prob], 2)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        adam["t"] += 1
-        B.ptycho_step([prob], [g], [adam], kind=B.LOSS_AMPLITUDE, eps=1e-6, scale=1.0,
-                      workspace=ws, stream=stream)
-
-    # Kernel timing: with two or more warm-up steps, every launch of the
-    # warm-up steps after the first is bracketed with HIP events (the
-    # per-class breakdown), and in the timed region only the launches of the
-    # class with the most time, whose figures the roofline object reports.
-    # With fewer warm-up steps every launch of the timed region is bracketed.
-    timing = not args.no_kernel_timing
-    split = timing and args.warmup >= 2
-    kern_warm, n_warm = {}, 0
-    for i in range(args.warmup):
-        if split and i == 1:
-            torch.cuda.synchronize()
-            B.ptycho_profile(True)
-        step()
-    torch.cuda.synchronize()
-    if split:
-        kern_warm, n_warm = B.ptycho_profile_read(), args.warmup - 1
-        B.ptycho_profile(False)
-    dom_warm = max(kern_warm, key=lambda k: kern_warm[k][0]) if kern_warm else None
-    if timing:
-        B.ptycho_profile(True)
-        if dom_warm is not None:
-            B.ptycho_profile_classes([dom_warm])
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = {}
-    if timing:
-        kern = B.ptycho_profile_read()
-        B.ptycho_profile(False)
-    status = B.ptycho_status(ws, 0)
-    if status != 0:
-        print(f"device status {status}: a window left the object", file=sys.stderr)
-        return 1
-    ms = (t1 - t0) * 1e3 / args.steps
-    pm = K * L * M * w.Ns
-    value = pm / (ms * 1e-3)
-    b_step = step_alg_bytes(K, L, M, N, H, W)
-
-    roof = None
-    kern_out = {}
-    if kern:
-        # per-class figures: the timed region's where it bracketed the class,
-        # else those of the profiled warm-up steps
-        for src, nsteps in ((kern_warm, n_warm), (kern, args.steps)):
-            for name, (tot, n) in src.items():
-                if n:
-                    kern_out[name] = dict(ms_per_step=tot / nsteps, launches_per_step=n / nsteps,
-                                          avg_launch_us=1e3 * tot / n,
-                                          timed_region=src is kern)
-        dom = dom_warm or max(kern_out, key=lambda k: kern_out[k]["ms_per_step"])
-        d = kern_out[dom]
-        per_launch = alg_bytes(dom, K, L, M, N, H, W) / d["launches_per_step"]
-        achieved = per_launch / (d["avg_launch_us"] * 1e-6) / 1e9
-        traffic = None if czt else measured_traffic(w.name, dom)
-        roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if traffic is None else round(traffic / 1e9, 4),
-                    traffic_unit="GB per launch",
-                    alg_bytes_per_launch=per_launch, avg_launch_us=round(d["avg_launch_us"], 2))
-        for name, d in kern_out.items():
-            b = alg_bytes(name, K, L, M, N, H, W)
-            if b:
-                d["alg_GBps"] = round(b / (d["ms_per_step"] * 1e-3) / 1e9, 1)
-    graph = None
-    if args.graph:
-        graph = graph_timing(B, prob, g, ws, args.steps, args.warmup)
+    w = synth.get_workload(args.workload)
+    main_run = time_workload(B, w, dev, args, czt, "main")
+    truth, start = main_run.pop("_truth"), main_run.pop("_start")
     cpu = None
     if not args.no_cpu_baseline:
+        print("[main] CPU baseline (oracle, one thread)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, truth, start)
+    del truth, start
+    extra = {}
+    for name in [x for x in args.extra.split(",") if x and x != args.workload]:
+        r = time_workload(B, synth.get_workload(name), dev, args, czt, "extra")
+        r.pop("_truth"), r.pop("_start")
+        extra[name] = r
     copy_gbps = copy_bandwidth()
     serving = None
-    pads = [round(p, 4) if isinstance(p, float) else int(p) for p in prob.pads]
-    prop = ("exact-ratio propagator (scaled DFT by Bluestein's method, FFT length 2N), ratios "
-            if czt else "zero-padded DFT, pads ")
     if not args.no_serving:
         from paper_2311_14780_amd import serving as S
-        del g, adam, ws, prob
         torch.cuda.empty_cache()
         serving = S.run_stream(args.serving_jobs, args.serving_iters,
                                log=lambda m: print(m, file=sys.stderr, flush=True))
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "pattern-modes/s",
+        "metric": METRIC, "value": main_run["value"], "unit": "pattern-modes/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": main_run["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": (f"{w.name}: {L} wavelengths (harmonics {'/'.join(map(str, w.harmonics))}) "
-                                f"x {M} probe modes, probe {N}x{N}, object {H}x{W} per wavelength, "
-                                f"{K} positions ({w.scan}), {prop}{'/'.join(map(str, pads))}, "
-                                f"{w.photons:.0e} photons/pattern; step = loss + gradients + Adam"),
-                   "K": K, "L": L, "M": M, "N": N, "H": H, "W": W, "pads": pads,
-                   "propagator": "exact-ratio" if czt else "zero-padded DFT",
-                   "parallelism": "single GPU"},
-        "step_roofline": {"alg_bytes_per_step": b_step,
-                          "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),
-                          "frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "roofline": roof,
+        "config": main_run["config"],
+        "step_roofline": main_run["step_roofline"],
+        "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
-        "graph": graph,
+        "graph": main_run["graph"],
         "context": {"device_copy_GBps": round(copy_gbps, 1),
                     "note": "torch device-to-device copy of 1 GiB, read + write bytes"},
+        "extra": extra or None,
         "serving": serving,
-        "kernels": kern_out,
-        "kernel_timing": (None if not timing else
-                          "HIP events around the dominant class's launches in the timed region; "
-                          "other classes from the bracketed warm-up steps" if split else
-                          "HIP events around every launch of the timed region"),
+        "kernels": main_run["kernels"],
+        "kernel_timing": main_run["kernel_timing"],
     }
     print(json.dumps(out))
     return 0

@@ -48,8 +48,10 @@
  *    such an error no output has been touched.  Window bounds depend on the
  *    device-resident positions and are checked on the device: when a window
  *    leaves the object, no out-of-bounds access happens, the loss is set to
- *    NaN, the gradients are left zeroed and ptycho_status() reports
- *    PTYCHO_ERANGE for that job.
+ *    NaN, the gradients are left zeroed, ptycho_step leaves that job's
+ *    variables and Adam moments bitwise unchanged, and ptycho_status()
+ *    reports PTYCHO_ERANGE for that job.  The other jobs of the call are
+ *    not affected.
  *  - Results are deterministic: no floating-point atomics are used; sums run
  *    in a fixed order that does not depend on the workspace size or on the
  *    other jobs of a call.
@@ -202,7 +204,16 @@ int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t
 int32_t ptycho_forward(const ptycho_job_t* jobs, int32_t n_jobs, float* const* intensity,
                        void* workspace, size_t workspace_bytes, void* stream);
 
-/* Loss and gradients for each job (grads[j] belongs to jobs[j]). */
+/* Loss and gradients for each job (grads[j] belongs to jobs[j]): the model
+   of Eq. 1 evaluated in the order of Eq. 2, one of the losses of Section
+   "Universal Ptychography Algorithm based on Automatic Differentiation"
+   summed over positions and pixels, and the exact gradient of that loss with
+   respect to every variable whose output pointer is non-NULL -- the reverse
+   pass of Fig. 1B (intensity residual back through the measurement, the
+   conjugate propagator, the probe-object product and the Fourier shift),
+   written out by hand instead of taken by automatic differentiation.
+   Outputs are overwritten (not accumulated).  The workspace is scratch for
+   the call; ptycho_status() reads the per-job window check from it. */
 int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_t* loss,
                          const ptycho_grads_t* grads, void* workspace, size_t workspace_bytes,
                          void* stream);

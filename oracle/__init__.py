@@ -16,13 +16,15 @@ which reduces to the zero-padded DFT at integer ratios and has closed forms
 for discrete plane waves), closed-form shifts of single Fourier
 modes, Parseval, the adjoint identity of every linear operator, zero loss and
 gradient at the noiseless truth, invariance under unitary mode mixing, gauge
-identities of the gradient and central finite differences.
+identities of the gradient and central finite differences.  The Adam step
+(the paper's optimiser) is pinned by a hand-derived three-step table with
+non-zero moments, the constant-gradient closed form and scale invariance.
 """
 
 from .model import (
     split_positions, shift_patch, shift_patch_adjoint, propagate,
     propagate_adjoint, is_ratio, scaled_dft_matrix, propagate_dalpha, resample, resample_adjoint,
-    forward, loss_grad, pointwise_loss, regulariser, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN,
+    forward, loss_grad, pointwise_loss, regulariser, adam_step, LOSS_AMPLITUDE, LOSS_POISSON, LOSS_GAUSSIAN,
     LOSS_VJP, LOSS_MIXED,
 )
 
@@ -30,5 +32,5 @@ __all__ = [
     "split_positions", "shift_patch", "shift_patch_adjoint", "propagate",
     "propagate_adjoint", "is_ratio", "scaled_dft_matrix", "propagate_dalpha", "resample",
     "resample_adjoint", "forward", "loss_grad", "pointwise_loss", "LOSS_AMPLITUDE", "LOSS_POISSON",
-    "LOSS_GAUSSIAN", "LOSS_VJP", "LOSS_MIXED", "regulariser",
+    "LOSS_GAUSSIAN", "LOSS_VJP", "LOSS_MIXED", "regulariser", "adam_step",
 ]

@@ -356,3 +356,43 @@ def loss_grad(obj, probe, pos, pads, measured, kind=LOSS_AMPLITUDE, eps=1e-6,
     return dict(loss=total, g_object=g_obj[:, 0] if squeeze else g_obj,
                 g_probe=g_prb, g_pos=g_pos, g_sigma=g_sig, g_background=g_bg,
                 g_ratio=g_ratio)
+
+
+# -------------------------------------------------------------------- Adam
+def adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (the optimiser the paper uses, Section "Universal
+    Ptychography Algorithm based on Automatic Differentiation"), elementwise
+    on real coordinates: a complex array is treated as its real and
+    imaginary parts.  Kingma and Ba's rule with step number t (1-based):
+
+        m <- beta1 m + (1 - beta1) g
+        v <- beta2 v + (1 - beta2) g^2
+        x <- x - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+
+    ``m`` and ``v`` are real arrays with one entry per real coordinate of x
+    (interleaved real, imaginary for a complex x).  Returns the new
+    (x, m, v) in float64 (complex128 for a complex x); the inputs are not
+    modified.
+    """
+    x = np.asarray(x)
+    cplx = np.iscomplexobj(x)
+    xr = (np.stack([x.real, x.imag], -1) if cplx else x).astype(np.float64).ravel()
+    g = np.asarray(g)
+    gr = (np.stack([g.real, g.imag], -1) if np.iscomplexobj(g) else g).astype(np.float64).ravel()
+    mr = np.asarray(m, np.float64).ravel()
+    vr = np.asarray(v, np.float64).ravel()
+    if not (xr.shape == gr.shape == mr.shape == vr.shape):
+        raise ValueError("x, g, m and v must have the same number of real coordinates")
+    if t < 1:
+        raise ValueError("the step number t is 1-based")
+    m_new = beta1 * mr + (1.0 - beta1) * gr
+    v_new = beta2 * vr + (1.0 - beta2) * gr * gr
+    m_hat = m_new / (1.0 - beta1 ** t)
+    v_hat = v_new / (1.0 - beta2 ** t)
+    x_new = xr - lr * m_hat / (np.sqrt(v_hat) + eps)
+    if cplx:
+        xc = x_new.reshape(x.shape + (2,))
+        x_new = xc[..., 0] + 1j * xc[..., 1]
+    else:
+        x_new = x_new.reshape(x.shape)
+    return x_new, m_new, v_new

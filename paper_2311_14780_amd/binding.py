@@ -139,6 +139,33 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check(t, name: str, dtype, shape=None, device=None, numel=None, where=True) -> None:
+    """Raises ValueError unless ``t`` (if not None) is a contiguous GPU tensor
+    of this dtype and shape (or element count) on ``device``.  The C ABI
+    receives bare device pointers and cannot know buffer sizes, so a wrong
+    shape would become an out-of-bounds device access; this is where it is
+    caught.  dtype and shape are checked before the device, so the checks
+    also run on tensors that were never moved to a GPU."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError(f"{name}: {t.numel()} elements, expected {int(numel)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensors passed to the library must be contiguous")
+    if not where:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU (device) tensor, got {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: on {t.device}, the job's object is on {device}")
+
+
 def _stream(stream) -> ctypes.c_void_p:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -188,7 +215,46 @@ class Problem:
     def Ns(self):
         return int(self.object.shape[1]) if self.object.dim() == 4 else 1
 
+    def validate(self) -> None:
+        """Dtype, shape and device of every tensor against the sizes the
+        probe and the positions define (raises ValueError)."""
+        if not isinstance(self.probe, torch.Tensor) or self.probe.dim() != 4 or \
+                self.probe.shape[-1] != self.probe.shape[-2]:
+            raise ValueError("probe: expected complex64 [L][M][N][N]")
+        if not isinstance(self.pos, torch.Tensor) or self.pos.dim() != 2:
+            raise ValueError("pos: expected float32 [K][2]")
+        if not isinstance(self.object, torch.Tensor) or self.object.dim() not in (3, 4):
+            raise ValueError("object: expected complex64 [L][H][W] or [L][Ns][H][W]")
+        K, L, M, N = self.K, self.L, self.M, self.N
+        dev = self.object.device
+        H, W = int(self.object.shape[-2]), int(self.object.shape[-1])
+        checks = [(self.object, "object", torch.complex64,
+                   (L, H, W) if self.object.dim() == 3 else (L, self.Ns, H, W)),
+                  (self.probe, "probe", torch.complex64, (L, M, N, N)),
+                  (self.pos, "pos", torch.float32, (K, 2)),
+                  (self.measured, "measured", torch.float32, (K, N, N)),
+                  (self.sigma, "sigma", torch.float32, (K,)),
+                  (self.background, "background", torch.float32, (N, N)),
+                  (self.mask, "mask", torch.uint8, (N, N))]
+        if self.resample is not None:
+            if len(self.resample) != 5:
+                raise ValueError("resample: expected (idx, w, ptr, col, val)")
+            idx, w, ptr, col, val = self.resample
+            n = N * N
+            checks += [(idx, "resample idx", torch.int32, (n, 4)),
+                       (w, "resample w", torch.float32, (n, 4)),
+                       (ptr, "resample ptr", torch.int32, (n + 1,)),
+                       (col, "resample col", torch.int32, (4 * n,)),
+                       (val, "resample val", torch.float32, (4 * n,))]
+        if len(self.pads) != L:
+            raise ValueError("one pad per wavelength is required")
+        for t, name, dt, shape in checks:  # dtype and shape of everything first
+            _check(t, name, dt, shape, where=False)
+        for t, name, dt, shape in checks:
+            _check(t, name, dt, shape, device=dev)
+
     def to_job(self) -> JobT:
+        self.validate()
         j = JobT()
         j.K, j.L, j.M, j.N = self.K, self.L, self.M, self.N
         j.H, j.W = int(self.object.shape[-2]), int(self.object.shape[-1])
@@ -253,13 +319,45 @@ def workspace_bytes_for_shapes(shapes: Sequence[tuple], which: int = 1, chunk: i
     return int(out.value)
 
 
+def _check_workspace(workspace, problems) -> None:
+    if workspace is None:
+        raise ValueError("a workspace tensor is required")
+    _check(workspace, "workspace", workspace.dtype if isinstance(workspace, torch.Tensor) else None,
+           device=problems[0].object.device)
+
+
 def ptycho_forward(problems: Sequence[Problem], intensities: Sequence[torch.Tensor],
                    workspace: torch.Tensor, stream=None) -> None:
+    if len(intensities) != len(problems):
+        raise ValueError("one intensity tensor per job is required")
+    for p, t in zip(problems, intensities):
+        _check(t, "intensity", torch.float32, (p.K, p.N, p.N), p.object.device)
+    _check_workspace(workspace, problems)
     outs = (_c_p * len(problems))(*[t.data_ptr() for t in intensities])
     code = lib().ptycho_forward(_jobs(problems), len(problems), outs, _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))
     if code:
         raise PtychoError(code, "ptycho_forward")
+
+
+_GRAD_KEYS = ("loss", "g_object", "g_probe", "g_pos", "g_sigma", "g_background", "g_ratio")
+
+
+def _check_grads(problems: Sequence[Problem], grads: Sequence[dict]) -> None:
+    if len(grads) != len(problems):
+        raise ValueError("one gradient dict per job is required")
+    for p, g in zip(problems, grads):
+        unknown = set(g) - set(_GRAD_KEYS)
+        if unknown:
+            raise ValueError(f"unknown gradient outputs {sorted(unknown)}")
+        dev = p.object.device
+        _check(g.get("loss"), "loss", torch.float32, (1,), dev)
+        _check(g.get("g_object"), "g_object", torch.complex64, tuple(p.object.shape), dev)
+        _check(g.get("g_probe"), "g_probe", torch.complex64, tuple(p.probe.shape), dev)
+        _check(g.get("g_pos"), "g_pos", torch.float32, (p.K, 2), dev)
+        _check(g.get("g_sigma"), "g_sigma", torch.float32, (p.K,), dev)
+        _check(g.get("g_background"), "g_background", torch.float32, (p.N, p.N), dev)
+        _check(g.get("g_ratio"), "g_ratio", torch.float32, (p.L,), dev)
 
 
 def _grads_array(grads: Sequence[dict]):
@@ -280,7 +378,10 @@ def ptycho_loss_grad(problems: Sequence[Problem], grads: Sequence[dict], kind: i
                      stream=None, **reg) -> None:
     """``reg``: noise_var (mixed-noise loss), l1, tv, tv_eps (regularisers)."""
     loss = _loss(kind, eps, scale, **reg)
-    code = lib().ptycho_loss_grad(_jobs(problems), len(problems), ctypes.byref(loss),
+    jobs = _jobs(problems)
+    _check_grads(problems, grads)
+    _check_workspace(workspace, problems)
+    code = lib().ptycho_loss_grad(jobs, len(problems), ctypes.byref(loss),
                                   _grads_array(grads), _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), _stream(stream))
     if code:
@@ -291,6 +392,18 @@ def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequen
                 kind: int = 0, eps: float = 1e-6, scale: float = 1.0,
                 workspace: torch.Tensor = None, stream=None, **reg) -> None:
     loss = _loss(kind, eps, scale, **reg)
+    jobs = _jobs(problems)
+    _check_grads(problems, grads)
+    _check_workspace(workspace, problems)
+    if len(adam) != len(problems):
+        raise ValueError("one Adam dict per job is required")
+    for p, a in zip(problems, adam):
+        dev = p.object.device
+        for var, t in (("object", p.object), ("probe", p.probe), ("pos", p.pos),
+                       ("sigma", p.sigma), ("background", p.background)):
+            n = 0 if t is None else t.numel() * (2 if t.is_complex() else 1)
+            for mv in ("m_", "v_"):
+                _check(a.get(mv + var), mv + var, torch.float32, device=dev, numel=n)
     arr = (AdamT * len(adam))()
     for i, a in enumerate(adam):
         arr[i].m_object, arr[i].v_object = _ptr(a.get("m_object")), _ptr(a.get("v_object"))
@@ -308,7 +421,7 @@ def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequen
         arr[i].beta2 = float(a.get("beta2", 0.999))
         arr[i].eps = float(a.get("eps", 1e-8))
         arr[i].t = int(a["t"])
-    code = lib().ptycho_step(_jobs(problems), len(problems), ctypes.byref(loss),
+    code = lib().ptycho_step(jobs, len(problems), ctypes.byref(loss),
                              _grads_array(grads), arr, _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream))
     if code:

@@ -272,12 +272,22 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
   return b;
 }
 
-// Bound on the segments one job adds to one phase: a chunk iteration adds
-// 5 per slot (row forward, column forward, column adjoint, row adjoint,
-// object gather), one per wavelength (probe reduction) and 4 more.
+// Bound on the segments one job adds to one phase.  Phase::add appends at
+// most one segment per (job, selector) and launch, so the bound follows from
+// the selectors each phase enumerates:
+//  - a chunk iteration: 5 per slot (row forward, column forward, column
+//    adjoint, row adjoint, object gather), one per wavelength (probe
+//    reduction) and one each for ramps, detector, background sum, finalise;
+//  - the prologue: one per gradient output (kVars + distance ratio), status,
+//    window check, and one chirp table per wavelength;
+//  - the epilogue: one regulariser segment per slot, the loss total and one
+//    Adam segment per variable.
+// The pool is sized from this bound, so no phase can overflow it and no call
+// fails after its first launch has been enqueued.
 constexpr int kSegsPerJob = 5 * kMaxL + PTYCHO_MAX_WAVELENGTHS + 4;
-static_assert(kSegsPerJob >= 2 * PTYCHO_MAX_WAVELENGTHS + kVars + 3,
-              "the prologue's segments (gradients, status, checks, chirp tables) fit too");
+static_assert(kSegsPerJob >= (kVars + 1) + 2 + PTYCHO_MAX_WAVELENGTHS, "prologue segments");
+static_assert(kSegsPerJob >= kMaxL + 1 + kVars, "epilogue segments");
+static_assert(PTYCHO_MAX_WAVELENGTHS <= kMaxL, "one slot per wavelength at least");
 
 size_t fixed_bytes(const ptycho_job_t* jobs, int n_jobs) {
   size_t b = align_up(sizeof(int) * n_jobs);                        // status
@@ -598,7 +608,7 @@ struct Phase {
 
 int upload_phase(const Call& c, const Phase& ph, hipStream_t s) {
   if (ph.segs.empty()) return PTYCHO_OK;
-  if (ph.segs.size() > static_cast<size_t>(kSegsPerJob) * c.n) return PTYCHO_EINVAL;
+  // ph.segs.size() <= kSegsPerJob * c.n by construction (see kSegsPerJob)
   LAUNCH(KC_TABLES, launch_write_table(reinterpret_cast<int*>(c.seg_pool),
                                        reinterpret_cast<const int*>(ph.segs.data()),
                                        static_cast<int>(ph.segs.size() * sizeof(Seg) / sizeof(int)), s));

@@ -1368,10 +1368,13 @@ __global__ void k_loss_total(Launch la, LossDev loss, float scale) {
 }
 
 // Adam on real coordinates.  Segment l selects the variable (0 object,
-// 1 probe, 2 positions); units are 1024-float blocks.
+// 1 probe, 2 positions, 3 sigma, 4 background); units are 1024-float blocks.
+// A job whose window check failed keeps its variables and moments: its
+// gradients are not valid, so no update is taken from them.
 __global__ __launch_bounds__(NT) void k_adam(Launch la) {
   const UnitRef r = decode<1>(la);
   const JobDev& jb = *r.jb;
+  if (*gmem(jb.status)) return;
   const int v = r.l;
   gf32* __restrict__ x = gmem(jb.var_flat[v]);
   const gf32* __restrict__ g = gmem(jb.grad_flat[v]);

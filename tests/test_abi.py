@@ -264,3 +264,67 @@ def test_profile_class_selection_on_the_host():
         B.ptycho_profile_classes(["no_such_class"])
     assert B.lib().ptycho_profile_classes(0) == 0
     B.ptycho_profile(False)  # also resets the mask to every class
+
+
+# ----------------------------------------------------- binding argument checks
+# The C ABI takes bare device pointers, so the binding is the only layer that
+# can see a tensor's dtype, shape and device.  These run without a GPU: dtype
+# and shape are checked before the device.
+
+def _cpu_problem(L=2, M=3, N=64, K=5, H=128, W=96, **over):
+    import torch
+    kw = dict(object=torch.zeros(L, H, W, dtype=torch.complex64),
+              probe=torch.zeros(L, M, N, N, dtype=torch.complex64),
+              pos=torch.zeros(K, 2), pads=(N,) * L,
+              measured=torch.zeros(K, N, N))
+    kw.update(over)
+    return B.Problem(**kw)
+
+
+@pytest.mark.parametrize("field,bad,what", [
+    ("object", "2d", "object"),
+    ("object", "real", "object"),
+    ("measured", "wrong_k", "measured"),
+    ("measured", "wrong_n", "measured"),
+    ("pos", "flat", "pos"),
+    ("sigma", "wrong_k", "sigma"),
+    ("background", "float64", "background"),
+    ("mask", "bool", "mask"),
+])
+def test_binding_rejects_bad_tensors(field, bad, what):
+    import torch
+    L, M, N, K, H, W = 2, 3, 64, 5, 128, 96
+    t = {
+        ("object", "2d"): torch.zeros(H, W, dtype=torch.complex64),
+        ("object", "real"): torch.zeros(L, H, W),
+        ("measured", "wrong_k"): torch.zeros(K + 1, N, N),
+        ("measured", "wrong_n"): torch.zeros(K, N, N + 1),
+        ("pos", "flat"): torch.zeros(2 * K),
+        ("sigma", "wrong_k"): torch.zeros(K - 1),
+        ("background", "float64"): torch.zeros(N, N, dtype=torch.float64),
+        ("mask", "bool"): torch.zeros(N, N, dtype=torch.bool),
+    }[(field, bad)]
+    p = _cpu_problem(L, M, N, K, H, W, **{field: t})
+    with pytest.raises(ValueError, match=what):
+        p.to_job()
+
+
+def test_binding_rejects_host_tensors_and_bad_gradients():
+    import torch
+    p = _cpu_problem()
+    # correct shapes and dtypes, but host memory: never handed to the library
+    with pytest.raises(ValueError, match="GPU"):
+        p.to_job()
+    with pytest.raises(ValueError, match="GPU"):
+        B.ptycho_loss_grad([p], [dict(loss=torch.zeros(1))], workspace=torch.zeros(8, dtype=torch.uint8))
+    # gradient outputs are checked against the job's shapes
+    for key, t in (("g_object", torch.zeros(2, 128, 96)),                      # real
+                   ("g_probe", torch.zeros(2, 3, 64, 63, dtype=torch.complex64)),
+                   ("g_pos", torch.zeros(5)),
+                   ("g_ratio", torch.zeros(3)),
+                   ("loss", torch.zeros(2)),
+                   ("g_bogus", torch.zeros(1))):
+        with pytest.raises(ValueError, match=key):
+            B._check_grads([p], [{key: t}])
+    with pytest.raises(ValueError):
+        B._check_grads([p, p], [{}])
