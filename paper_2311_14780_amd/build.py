@@ -21,8 +21,10 @@ BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+# -fno-signed-zeros lets the compiler drop additions of the zero padding
+# (x + 0.0 is x up to the sign of a zero result, which nothing here reads).
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fno-signed-zeros",
          "-I" + os.path.join(ROOT, "include")]
 SOURCES = ["kernels.hip", "api.cpp"]
 

@@ -256,13 +256,59 @@ struct DftComposite {
   }
 };
 
-template <bool INV> struct Dft<6, INV> : DftComposite<2, 3, INV> {};
+// Coprime R = R1 * R2 by the prime-factor (Good-Thomas) index maps, which
+// need no internal twiddle products: with input n = (R2 n1 + R1 n2) mod R and
+// output k = (e1 k1 + e2 k2) mod R, where e1 = R2 (R2^-1 mod R1) and
+// e2 = R1 (R1^-1 mod R2), n k = R2 n1 k1 + R1 n2 k2 (mod R), so the length-R
+// DFT is a length-R1 DFT over n1 for every n2 followed by a length-R2 DFT
+// over n2 for every k1.  Both maps are compile-time register renamings.
+constexpr int ct_inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;  // m == 1
+}
+template <int R1, int R2, bool INV>
+struct DftPfa {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr int R = R1 * R2;
+    constexpr int E1 = R2 * ct_inv_mod(R2 % R1, R1);
+    constexpr int E2 = R1 * ct_inv_mod(R1 % R2, R2);
+    float2 a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[(R2 * n1 + R1 * n2) % R];
+      Dft<R1, INV>::run(a[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[n2][k1];
+      Dft<R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[(E1 * k1 + E2 * k2) % R] = t[k2];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftPfa<2, 3, INV> {};
 template <bool INV> struct Dft<9, INV> : DftComposite<3, 3, INV> {};
-template <bool INV> struct Dft<10, INV> : DftComposite<2, 5, INV> {};
-template <bool INV> struct Dft<12, INV> : DftComposite<4, 3, INV> {};
-template <bool INV> struct Dft<14, INV> : DftComposite<2, 7, INV> {};
-template <bool INV> struct Dft<15, INV> : DftComposite<3, 5, INV> {};
+template <bool INV> struct Dft<10, INV> : DftPfa<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftPfa<4, 3, INV> {};
+template <bool INV> struct Dft<14, INV> : DftPfa<2, 7, INV> {};
+template <bool INV> struct Dft<15, INV> : DftPfa<3, 5, INV> {};
 template <bool INV> struct Dft<16, INV> : DftComposite<4, 4, INV> {};
+template <bool INV> struct Dft<18, INV> : DftPfa<2, 9, INV> {};
+template <bool INV> struct Dft<20, INV> : DftPfa<4, 5, INV> {};
+template <bool INV> struct Dft<21, INV> : DftPfa<3, 7, INV> {};
+template <bool INV> struct Dft<24, INV> : DftPfa<8, 3, INV> {};
+template <bool INV> struct Dft<25, INV> : DftComposite<5, 5, INV> {};
+template <bool INV> struct Dft<27, INV> : DftComposite<3, 9, INV> {};
+template <bool INV> struct Dft<28, INV> : DftPfa<4, 7, INV> {};
+template <bool INV> struct Dft<30, INV> : DftPfa<5, 6, INV> {};
+template <bool INV> struct Dft<32, INV> : DftComposite<4, 8, INV> {};
+template <bool INV> struct Dft<35, INV> : DftPfa<5, 7, INV> {};
 
 // ------------------------------------------------------------- radix plans
 template <int... Rs>
@@ -416,8 +462,13 @@ __device__ __forceinline__ void fft_first_load(PreIn<n, LINES, NT, LINE_FAST>& i
 // Twiddles loaded per butterfly: w and w^2 (one 16-byte load); the higher
 // powers are products w^r = w^(r/2) w^(r - r/2) (at most a few roundings).
 // Loading all R - 1 values per thread made the twiddle reads the largest
-// stream through the L1 cache (every thread reads its own copy).
-constexpr int kTwLoaded = 2;
+// stream through the L1 cache (every thread reads its own copy).  Short
+// transforms (n < 192: windows of 64 and 128, whose launches are small and
+// latency-bound) load every power instead, which keeps each twiddle at one
+// rounding: the Poisson-loss gradient weighs dim pixels by 1 - I^/I', so it
+// amplifies the transform error there (64 x 64 window, 1e4 photons: object
+// gradient 8e-5 -> 3e-5 relative L2 against the float64 oracle).
+constexpr int tw_loaded(int n) { return n < 192 ? 16 : 2; }
 
 // Twiddles of one pass for this thread's butterflies, [iteration][r - 1].
 template <int n, int R, int LINES, int NT>
@@ -425,7 +476,7 @@ struct PassTw {
   static constexpr int NB = n / R;
   static constexpr int BF = LINES * NB;
   static constexpr int ITER = (BF + NT - 1) / NT;
-  static constexpr int Q = R - 1 < kTwLoaded ? R - 1 : kTwLoaded;
+  static constexpr int Q = R - 1 < tw_loaded(n) ? R - 1 : tw_loaded(n);
   float2 w[ITER][Q > 0 ? Q : 1];
 };
 

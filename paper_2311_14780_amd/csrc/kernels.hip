@@ -98,6 +98,8 @@ __host__ __device__ constexpr bool adj_narrow(int N, int nl) {
 __host__ __device__ constexpr int col_group_adj(int N, int nl) {
   return adj_narrow(N, nl) ? 8 : (N <= 256 ? 16 : 8);
 }
+// Threads per block of the column adjoint instance.
+__host__ __device__ constexpr int col_adj_threads(int N, int nl) { return CNT; }
 // Row stride of the column adjoint's per-block partial sums ([C][L][stride]):
 // the most blocks per column set of any instance of N.
 __host__ __device__ constexpr int adj_stride(int N) { return N <= 128 ? N / 16 : N / 8; }
@@ -201,6 +203,30 @@ __device__ __forceinline__ UnitRef decode_xcd(const Launch& la) {
   const int x = b & 7, i = b >> 3, q = n >> 3, rem = n & 7;
   // XCD x holds q + (x < rem) blocks; they take the run starting at x q + min(x, rem)
   return decode<GX>(la, x * q + min(x, rem) + i);
+}
+
+// decode() for the column kernels of windows N >= 384: block b runs on XCD
+// x = b mod 8, and XCD x takes the column groups [x GX/8, (x+1) GX/8) of
+// every unit, units in ascending order.  Each XCD's L2 then keeps the probe columns of its own
+// column groups (every mode) while it works through the positions, instead
+// of fetching the whole probe of the wavelength again for every position;
+// neighbouring groups, whose 64-byte column segments share 128-byte lines,
+// stay on one XCD.  Without it every launch of the column forward and the
+// column adjoint (512 x 512 probe, 8 modes, 2500 positions) read the probe
+// once per position: about 42 GB of L2 misses on top of ~47 GB of planes
+// (column forward 98.6 -> 81.2 ms per step).  For N = 256 (3 modes, probe
+// 1.5 MB) the per-XCD runs of whole positions stay faster (column adjoint of
+// 400 positions x 4 wavelengths: 2.44 against 2.59 ms).
+template <int GX>
+__device__ __forceinline__ UnitRef decode_cols(const Launch& la) {
+  if constexpr (GX % 8 == 0 && GX * 8 >= 384) {
+    constexpr int PER = GX / 8;
+    const int b = blockIdx.x, x = b & 7, i = b >> 3;
+    const int unit = i / PER, sub = x * PER + (i - (i / PER) * PER);
+    return decode<GX>(la, unit * GX + sub);
+  } else {
+    return decode_xcd<GX>(la);
+  }
 }
 
 __global__ void k_write_table(TablePayload payload, int* __restrict__ dst, int n) {
@@ -362,10 +388,17 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
 // ---------------------------------------------------------- column forward
 // Osh = y-shift of X columns; Y_m = (1/sqrt(NL)) crop( DFT_NL_y( sigma P_m Osh ) )
 // units: (l, c) for the wavelengths whose DFT size is NL
+// Waves per SIMD the column forward is compiled for: instances that need a
+// few more than 128 VGPRs unbounded (DFT sizes 750 at N = 512, the Bluestein
+// lengths 2N) are held to 128, so that two 512-thread blocks share a CU.
+__host__ __device__ constexpr int col_fwd_waves(int N, int nl) {
+  return (N == 512 && nl == 750) ? 4 : 2;
+}
+
 template <int N, int NL>
-__global__ __launch_bounds__(CNT) void k_col_fwd(Launch la) {
+__global__ __launch_bounds__(CNT, col_fwd_waves(N, NL)) void k_col_fwd(Launch la) {
   constexpr int G = col_group<N>();
-  const UnitRef r = decode_xcd<N / G>(la);
+  const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   constexpr int LP = G + 1;
@@ -820,16 +853,17 @@ __global__ __launch_bounds__(NT) void k_resample_T(Launch la, int gx) {
 // RATIO: the exact-ratio instance that also computes the y-axis terms of
 // dL/d alpha (launches whose jobs want them).
 template <int N, int NL, bool GROUPED, bool RATIO>
-__global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Launch la) {
+__global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Launch la) {
   constexpr int G = col_group_adj(N, NL);
-  const UnitRef r = decode_xcd<N / G>(la);
+  constexpr int AT = col_adj_threads(N, NL);
+  const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   const bool want_probe = jb.g_probe != nullptr;
   constexpr int LP = G + 1;
-  constexpr int NE = N * G / CNT;
+  constexpr int NE = N * G / AT;
   __shared__ float2 buf[NL * LP];
-  __shared__ float red[CNT / 64];
+  __shared__ float red[AT / 64];
   extern __shared__ float2 pacc[];
   const int l = r.l, x0 = r.sub * G;
   const int tid = threadIdx.x;
@@ -838,7 +872,7 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
   const int cbeg = r.u * PG;
   const int cend = min(cbeg + PG, min(jb.C, jb.K - la.iter * jb.C));
   if (group_acc)
-    for (int e = tid; e < jb.M * N * G; e += CNT) pacc[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < jb.M * N * G; e += AT) pacc[e] = make_float2(0.f, 0.f);
   // (the transforms below synchronise the block before pacc is first used)
   for (int c = cbeg; c < cend; ++c) {
   const int k = la.iter * jb.C + c;
@@ -851,20 +885,20 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
   // recompute Ohat = ramp_y FFT_y(X) and Osh = IFFT_y(Ohat) / N
   auto ld_x = [&](int line, int i) { return ldv(X, i * N + line); };
   auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ldv(ry, i)); };
-  fft_lines<N, false, G, CNT, LP, true>(buf, twN, ld_x, st_ramp);
+  fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_x, st_ramp);
   float2 ohat[NE], o[NE], go[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
-    const int e = tid + q * CNT, line = e % G, i = e / G;
+    const int e = tid + q * AT, line = e % G, i = e / G;
     ohat[q] = buf[i * LP + line];
   }
   auto ld_buf = [&](int line, int i) { return buf[i * LP + line]; };
   auto st_buf = [&](int line, int i, float2 v) { buf[i * LP + line] = v; };
-  fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_buf);
+  fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
   constexpr float invN = 1.0f / N;
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
-    const int e = tid + q * CNT, line = e % G, i = e / G;
+    const int e = tid + q * AT, line = e % G, i = e / G;
     o[q] = cscale(buf[i * LP + line], invN);
     go[q] = make_float2(0.f, 0.f);
   }
@@ -893,7 +927,7 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
   // the single-position zero-padded instances; the grouped and the
   // exact-ratio (length 2N) instances have no registers left for them.
   constexpr bool PREFETCH = !GROUPED && !CZT;
-  using ZIn = PreIn<NL, G, CNT, true>;
+  using ZIn = PreIn<NL, G, AT, true>;
   auto zload = [&](int m, ZIn& zin) {
     const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
     fft_first_load(zin, [&](int line, int t) { return zin_at(Zm, line, t); });
@@ -919,11 +953,11 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
         auto ld_u = [&](int line, int t) {
           return cscale(zin_at(Z, line, t), static_cast<float>(t - N / 2));
         };
-        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_u, st_hc);
-        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
+        fft_lines<NL, false, G, AT, LP, true>(buf, twL, ld_u, st_hc);
+        fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_b, st_chic);
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-          const int e = tid + q * CNT, line = e % G, i = e / G;
+          const int e = tid + q * AT, line = e % G, i = e / G;
           const float2 cu = buf[i * LP + line];
           const float2 ps = cscale(cmul(ldv(P, i * N + line), o[q]), sig);
           rsum += static_cast<float>(i) * (cu.y * ps.x - cu.x * ps.y);
@@ -934,20 +968,20 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
     if constexpr (!PREFETCH) {
       auto ld_z = [&](int line, int t) { return zin_at(Z, line, t); };
       if constexpr (CZT) {
-        fft_lines<NL, false, G, CNT, LP, true>(buf, twL, ld_z, st_hc);
-        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_b, st_chic);
+        fft_lines<NL, false, G, AT, LP, true>(buf, twL, ld_z, st_hc);
+        fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_b, st_chic);
       } else {
-        fft_lines<NL, true, G, CNT, LP, true>(buf, twL, ld_z, st_chi);
+        fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_z, st_chi);
       }
     } else {
       ZIn znext;
       if (m + 1 < jb.M) zload(m + 1, znext);
-      fft_lines<NL, true, G, CNT, LP, true>(buf, twL, zcur, st_chi);
+      fft_lines<NL, true, G, AT, LP, true>(buf, twL, zcur, st_chi);
       zcur = znext;
     }
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * CNT, line = e % G, i = e / G;
+      const int e = tid + q * AT, line = e % G, i = e / G;
       const float2 chi = buf[i * LP + line];
       const float2 p = ldv(P, i * N + line);
       const float2 pc = cmulconj(p, chi);  // conj(P) chi
@@ -968,13 +1002,13 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
     __syncthreads();
   }
   {
-    const float s = block_sum<CNT>(sgsum, red);
+    const float s = block_sum<AT>(sgsum, red);
     if (tid == 0)
       gmem(jb.sg_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] = s;
   }
   if (want_ratio) {
     const double a = jb.czt_alpha[l];
-    const float s = block_sum<CNT>(rsum, red);
+    const float s = block_sum<AT>(rsum, red);
     if (tid == 0)
       gmem(jb.rb_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] =
           static_cast<float>(2.0 * kPi / (a * a)) * s;
@@ -982,15 +1016,15 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
   // Ghat = FFT_y(G_Osh): y-position derivative and adjoint y-shift
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
-    const int e = tid + q * CNT, line = e % G, i = e / G;
+    const int e = tid + q * AT, line = e % G, i = e / G;
     buf[i * LP + line] = go[q];
   }
   __syncthreads();
-  fft_lines<N, false, G, CNT, LP, true>(buf, twN, ld_buf, st_buf);
+  fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
   float dsum = 0.f;
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
-    const int e = tid + q * CNT, line = e % G, i = e / G;
+    const int e = tid + q * AT, line = e % G, i = e / G;
     const float2 gh = buf[i * LP + line];
     const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
     // Re( conj(gh) * (i nu ohat) )
@@ -1000,8 +1034,8 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
   __syncthreads();
   gf2* __restrict__ GX = gmem(jb.GX) + (static_cast<size_t>(c) * jb.L + l) * N * N + x0;
   auto st_gx = [&](int line, int i, float2 v) { stv(GX, i * N + line, cscale(v, invN)); };
-  fft_lines<N, true, G, CNT, LP, true>(buf, twN, ld_buf, st_gx);
-  const float s = block_sum<CNT>(dsum, red);
+  fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_gx);
+  const float s = block_sum<AT>(dsum, red);
   if (tid == 0)
     gmem(jb.dy_part)[(static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub] = s * invN;
   }  // positions of the group
@@ -1010,7 +1044,7 @@ __global__ __launch_bounds__(CNT, adj_narrow(N, NL) ? 4 : 2) void k_col_adj(Laun
     for (int m = 0; m < jb.M; ++m) {
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * CNT, line = e % G, i = e / G;
+        const int e = tid + q * AT, line = e % G, i = e / G;
         stv(Zg + static_cast<size_t>(m) * N * N, i * N + line, pacc[(m * N + i) * G + line]);
       }
     }
@@ -1591,7 +1625,7 @@ template <int NN, int NL, bool RATIO>
 hipError_t launch_col_adj_inst(dim3 g, const Launch& la, size_t dyn_lds, bool grouped,
                                hipStream_t s) {
   if (!grouped) {
-    hipLaunchKernelGGL((k_col_adj<NN, NL, false, RATIO>), g, dim3(CNT), 0, s, la);
+    hipLaunchKernelGGL((k_col_adj<NN, NL, false, RATIO>), g, dim3(col_adj_threads(NN, NL)), 0, s, la);
     return hipGetLastError();
   }
   if (dyn_lds) {
@@ -1600,7 +1634,7 @@ hipError_t launch_col_adj_inst(dim3 g, const Launch& la, size_t dyn_lds, bool gr
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn_lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_col_adj<NN, NL, true, RATIO>), g, dim3(CNT), dyn_lds, s, la);
+  hipLaunchKernelGGL((k_col_adj<NN, NL, true, RATIO>), g, dim3(col_adj_threads(NN, NL)), dyn_lds, s, la);
   return hipGetLastError();
 }
 

@@ -208,6 +208,7 @@ def compare(got, ref, tol_grad=1e-4, tol_loss=1e-5,
     relatively by tol_loss.  Prints every figure; raises with all of them
     on failure."""
     tol_pp = 10.0 * tol_grad if tol_pp is None else tol_pp
+    assert np.isfinite(ref["loss"]) and np.isfinite(got["loss"]), (got["loss"], ref["loss"])
     errs = {"loss": abs(got["loss"] - ref["loss"]) / max(abs(ref["loss"]), 1e-30)}
     bad = {}
     if errs["loss"] > tol_loss:
