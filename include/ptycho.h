@@ -218,6 +218,29 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
                          const ptycho_grads_t* grads, void* workspace, size_t workspace_bytes,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   loss and gradients as ptycho_loss_grad, with the library's own scratch
+   instead of a caller workspace.  The scratch is a static device array of
+   PTYCHO_NOALLOC_SCRATCH_BYTES per GPU, created when the library is loaded
+   and held until the process ends; this call allocates nothing (no
+   hipMalloc/hipFree, no events: profiling does not bracket it).  Jobs whose
+   smallest workspace (one position per chunk, see ptycho_workspace_bytes)
+   exceeds the scratch are rejected with PTYCHO_ENOSPC before anything is
+   enqueued; larger scans run in more, smaller position chunks, with results
+   bitwise equal to ptycho_loss_grad.  The first call on a device copies the
+   twiddle tables into their static array (a synchronous copy, no
+   allocation).  Every call on one GPU shares that GPU's scratch and leaves
+   its contents behind (each call initialises everything it reads): calls
+   that overlap on one GPU race, so serialise them (one stream, or events).
+   A window outside the object sets that job's loss to NaN and leaves its
+   gradients zeroed, as in ptycho_loss_grad; ptycho_status() cannot read this
+   call's status (the caller has no pointer to the scratch). */
+#define PTYCHO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t ptycho_loss_grad_noalloc(const ptycho_job_t* jobs, int32_t n_jobs,
+                                 const ptycho_loss_t* loss, const ptycho_grads_t* grads,
+                                 void* stream);
+
 /* Loss, gradients and one Adam update of object, probe, positions, power
    coefficients and background of each job, in place.  grads[j].g_* must be non-NULL for every variable whose
    learning rate is non-zero (they receive the gradient at the state before
@@ -258,7 +281,9 @@ int32_t ptycho_profile_classes(uint32_t class_mask);
 /* Static description of an error code. */
 const char* ptycho_error_string(int32_t code);
 
-/* Frees the library's cached device tables (twiddles) on every device. */
+/* Forgets the library's device tables (twiddles, kept in static device
+   arrays), so that the next call on each device fills them again, and frees
+   the profiling events. */
 void ptycho_release(void);
 
 #ifdef __cplusplus

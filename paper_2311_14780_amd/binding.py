@@ -102,6 +102,10 @@ def lib():
         L.ptycho_loss_grad.argtypes = [ctypes.POINTER(JobT), _c_i32, ctypes.POINTER(LossT),
                                        ctypes.POINTER(GradsT), _c_p, ctypes.c_size_t, _c_p]
         L.ptycho_loss_grad.restype = _c_i32
+        L.ptycho_loss_grad_noalloc.argtypes = [ctypes.POINTER(JobT), _c_i32,
+                                               ctypes.POINTER(LossT), ctypes.POINTER(GradsT),
+                                               _c_p]
+        L.ptycho_loss_grad_noalloc.restype = _c_i32
         L.ptycho_step.argtypes = [ctypes.POINTER(JobT), _c_i32, ctypes.POINTER(LossT),
                                   ctypes.POINTER(GradsT), ctypes.POINTER(AdamT), _c_p,
                                   ctypes.c_size_t, _c_p]
@@ -386,6 +390,22 @@ def ptycho_loss_grad(problems: Sequence[Problem], grads: Sequence[dict], kind: i
                                   workspace.numel() * workspace.element_size(), _stream(stream))
     if code:
         raise PtychoError(code, "ptycho_loss_grad")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PTYCHO_NOALLOC_SCRATCH_BYTES
+
+
+def ptycho_loss_grad_noalloc(problems: Sequence[Problem], grads: Sequence[dict], kind: int = 0,
+                             eps: float = 1e-6, scale: float = 1.0, stream=None, **reg) -> None:
+    """ptycho_loss_grad on the library's static scratch (no workspace, no
+    device allocation); calls on one GPU must not overlap."""
+    loss = _loss(kind, eps, scale, **reg)
+    jobs = _jobs(problems)
+    _check_grads(problems, grads)
+    code = lib().ptycho_loss_grad_noalloc(jobs, len(problems), ctypes.byref(loss),
+                                          _grads_array(grads), _stream(stream))
+    if code:
+        raise PtychoError(code, "ptycho_loss_grad_noalloc")
 
 
 def ptycho_step(problems: Sequence[Problem], grads: Sequence[dict], adam: Sequence[dict],

@@ -24,12 +24,28 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // ------------------------------------------------------------ twiddle tables
+// The per-pass twiddles of every compiled length live in one static device
+// array (each GPU holds its own copy from module load to process end); the
+// first call on a device copies the float64-built values into it.  No entry
+// point allocates device memory for them.
+constexpr size_t kTwCapacity = 16384;  // float2 entries (all lengths need 9728)
+__device__ __align__(256) float2 tw_store[kTwCapacity];
+
 struct DeviceTables {
-  float2* base = nullptr;
+  float2* base = nullptr;  // device address of tw_store on that device
   std::map<int, size_t> offset;  // length -> element offset
 };
 std::mutex g_mutex;
 std::map<int, DeviceTables> g_tables;  // device id -> tables
+
+// Scratch of the allocation-free entry point (ptycho_loss_grad_noalloc): a
+// file-scope device array of fixed size.  In host code `scratch` only names
+// the symbol; its address on a device comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is passed
+// to kernels and copies.
+constexpr size_t kScratchBytes = PTYCHO_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::map<int, void*> g_scratch;  // device id -> device address of scratch
 
 const int kLengths[] = {64,  72,  80,  84,  90,  96,  128, 140, 150, 168, 189, 256, 280, 300,
                         315, 336, 343, 375, 384, 420, 480, 512, 560, 600, 675, 750, 768, 1024};
@@ -65,14 +81,29 @@ int init_twiddles() {
     }
     while (host.size() % 32) host.push_back(make_float2(0.f, 0.f));
   }
-  if (hipMalloc(&t.base, host.size() * sizeof(float2)) != hipSuccess) return PTYCHO_EHIP;
+  if (host.size() > kTwCapacity) return PTYCHO_EHIP;
+  void* base = nullptr;
+  if (hipGetSymbolAddress(&base, HIP_SYMBOL(tw_store)) != hipSuccess || !base) return PTYCHO_EHIP;
+  t.base = static_cast<float2*>(base);
   if (hipMemcpy(t.base, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    (void)hipFree(t.base);
+      hipSuccess)
     return PTYCHO_EHIP;
-  }
   g_tables[dev] = t;
   return PTYCHO_OK;
+}
+
+// Device address of the static scratch on the current device (looked up
+// once per device), or null on a runtime error.
+void* scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+  g_scratch[dev] = ptr;
+  return ptr;
 }
 
 const float2* twiddles(int n) {
@@ -87,14 +118,10 @@ const float2* twiddles(int n) {
 }
 
 void release_twiddles() {
+  // the tables are static device arrays: forgetting them makes the next call
+  // fill them again
   std::lock_guard<std::mutex> lock(g_mutex);
-  int cur = 0;
-  const bool have = hipGetDevice(&cur) == hipSuccess;
-  for (auto& kv : g_tables) {
-    if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second.base);
-  }
   g_tables.clear();
-  if (have) (void)hipSetDevice(cur);
 }
 
 }  // namespace ptycho
@@ -155,7 +182,8 @@ struct ProfScope {
   int cls;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+  ProfScope(int c, hipStream_t st, bool allowed) : cls(c), s(st) {
+    if (!allowed) return;  // the allocation-free entry point creates no events
     std::lock_guard<std::mutex> lock(g_prof_mutex);
     if (!g_prof_on || !((g_prof_mask >> cls) & 1u)) return;
     a = prof_event();
@@ -340,6 +368,7 @@ struct Call {
   std::vector<JobDev> host_jobs;
   std::vector<int> chunk;   // C per job
   std::vector<int> pgroup;  // probe-gradient group size per job
+  bool profile = true;      // launches may be bracketed by profiling events
 };
 
 // Positions whose probe-gradient terms are summed in one column-adjoint
@@ -602,7 +631,7 @@ struct Phase {
 // A launch, timed per kernel class when profiling is on.
 #define LAUNCH(cls, x)                         \
   do {                                         \
-    ProfScope prof_scope_(cls, s);             \
+    ProfScope prof_scope_(cls, s, c.profile);  \
     if ((x) != hipSuccess) return PTYCHO_EHIP; \
   } while (0)
 
@@ -930,6 +959,37 @@ int32_t ptycho_loss_grad(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_
                    loss->l1, loss->tv, loss->tv_eps};
   c.scale = loss->scale;
   return run_call(c, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int32_t ptycho_loss_grad_noalloc(const ptycho_job_t* jobs, int32_t n_jobs,
+                                 const ptycho_loss_t* loss, const ptycho_grads_t* grads,
+                                 void* stream) {
+  int e = common_checks(jobs, n_jobs, true);
+  if (e) return e;
+  if (!loss || !grads) return PTYCHO_EINVAL;
+  e = check_loss(*loss);
+  if (e) return e;
+  // the smallest workspace these jobs can run in (one position per chunk)
+  size_t need = 0;
+  e = ptycho_workspace_bytes(jobs, n_jobs, 1, 1, &need);
+  if (e) return e;
+  if (need > kScratchBytes) return PTYCHO_ENOSPC;
+  e = init_twiddles();
+  if (e) return e;
+  void* ws = scratch_address();
+  if (!ws) return PTYCHO_EHIP;
+  Call c;
+  c.which = 1;
+  c.n = n_jobs;
+  c.jobs = jobs;
+  c.grads = grads;
+  c.adam = nullptr;
+  c.out = nullptr;
+  c.loss = LossDev{loss->kind, loss->eps, 2.0f * loss->scale, loss->noise_var,
+                   loss->l1, loss->tv, loss->tv_eps};
+  c.scale = loss->scale;
+  c.profile = false;
+  return run_call(c, ws, kScratchBytes, static_cast<hipStream_t>(stream));
 }
 
 int32_t ptycho_step(const ptycho_job_t* jobs, int32_t n_jobs, const ptycho_loss_t* loss,
