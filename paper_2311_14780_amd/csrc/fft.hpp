@@ -425,6 +425,27 @@ struct FirstRadixOf<Radices<Rs...>> {
   static constexpr int value = FirstRadix<Rs...>::value;
 };
 
+// Synchronisation of a transform.  With NT = 64 the lines belong to one
+// wave (its own LDS region): a wave's LDS operations complete in program
+// order, so the passes need only a compiler fence between the reads and the
+// writes of the in-place buffer, and waves never wait for each other (a
+// wave stalled on a global load does not hold the others of its block).
+// With NT > 64 the whole workgroup shares the lines and each pass ends with
+// a workgroup barrier.
+template <int NT>
+__device__ __forceinline__ int fft_tid() {
+  return NT == 64 ? static_cast<int>(threadIdx.x & 63u) : static_cast<int>(threadIdx.x);
+}
+template <int NT>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Inputs of the first pass of an FFT, loaded ahead of time with
 // fft_first_load and handed to fft_lines in place of a load functor, so that
 // the loads of the next transform are in flight during the current one.
@@ -446,7 +467,7 @@ template <int n, int LINES, int NT, bool LINE_FAST, class Load>
 __device__ __forceinline__ void fft_first_load(PreIn<n, LINES, NT, LINE_FAST>& in,
                                                const Load& load) {
   using P = PreIn<n, LINES, NT, LINE_FAST>;
-  const int tid = threadIdx.x;
+  const int tid = fft_tid<NT>();
 #pragma unroll
   for (int it = 0; it < P::ITER; ++it) {
     const int b = tid + it * NT;
@@ -485,7 +506,7 @@ template <int n, int R, int Ns, int TOFF, int LINES, int NT, bool LINE_FAST, cla
 __device__ __forceinline__ void load_pass_tw(Tw tw, PassTw<n, R, LINES, NT>& out) {
   if constexpr (Ns > 1) {
     using P = PassTw<n, R, LINES, NT>;
-    const int tid = threadIdx.x;
+    const int tid = fft_tid<NT>();
 #pragma unroll
     for (int it = 0; it < P::ITER; ++it) {
       const int b = tid + it * NT;
@@ -519,7 +540,7 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
   // writes: o = base + r Ns, base = (j / Ns) Ns R + j % Ns; all o of a
   // butterfly lie in one aligned block of Ns R elements
   constexpr int WR_MODE = (16 % (Ns * R) == 0) ? 1 : 0;
-  const int tid = threadIdx.x;
+  const int tid = fft_tid<NT>();
   float2 v[ITER][R];
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
@@ -552,7 +573,7 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
     }
   }
   prefetch();
-  __syncthreads();  // every read of this pass precedes any write (in-place LDS)
+  fft_sync<NT>();  // every read of this pass precedes any write (in-place LDS)
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int b = tid + it * NT;
@@ -569,7 +590,7 @@ __device__ __forceinline__ void stockham_pass(Buf buf, const PassTw<n, R, LINES,
       }
     }
   }
-  __syncthreads();
+  fft_sync<NT>();
 }
 
 
@@ -599,7 +620,8 @@ __device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const PassTw<n, R, 
 // outputs via store(line, i, value).  `buf` must hold LINES lines laid out as
 // Lds<n, LP, LINE_FAST>.  The call begins with the first pass's reads (the
 // caller must have synchronised any earlier use of `buf`) and ends with a
-// workgroup barrier.  Unnormalised in both directions.
+// workgroup barrier (NT = 64: a wave fence; the lines and `buf` are then the
+// calling wave's own).  Unnormalised in both directions.
 template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Buf, class Tw,
           class Load, class Store>
 __device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, const Store& store) {

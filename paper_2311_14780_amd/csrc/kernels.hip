@@ -477,6 +477,10 @@ __global__ __launch_bounds__(CNT, col_fwd_waves(N, NL)) void k_col_fwd(Launch la
 }
 
 // ------------------------------------------------------------ detector rows
+// The detector-row passes below run per wave: the RB rows (and `buf`, `acc`,
+// `Yr`, `psi`) are the calling wave's own, and the transforms synchronise the
+// wave only (see fft_sync), so a wave waiting for its rows' loads does not
+// hold the other waves of the block.
 // Row pass of the padded DFT for one (l, m) and RB detector rows:
 // Psi[u][:] = (1/sqrt(NL)) crop( DFT_NL_x( Y[u][:] ) ), acc += |Psi|^2.
 // Kept out of line so that each DFT size gets its own register allocation
@@ -495,7 +499,7 @@ __device__ __noinline__ void det_rows_fwd(lf2* buf, lf32* acc, gf2* __restrict__
       acc[line * N + u] += cabs2(v);
     }
   };
-  fft_lines<NL, false, RB, NT, LP, false>(buf, twL, ld, st);
+  fft_lines<NL, false, RB, 64, LP, false>(buf, twL, ld, st);
 }
 
 // Zero-padded adjoint row pass: recomputes Psi = crop(DFT(Y)) from the kept
@@ -515,7 +519,7 @@ __device__ __noinline__ void det_rows_recomp(lf2* buf, const lf32* acc, gf2* __r
     if (u >= NL) u -= NL;
     if (u < N) stv(buf, Ix::at(line, u), cscale(v, ps * acc[line * N + u]));
   };
-  fft_lines<NL, false, RB, NT, LP, false>(buf, twL, ld, st);
+  fft_lines<NL, false, RB, 64, LP, false>(buf, twL, ld, st);
   auto ld2 = [&](int line, int t) {
     int u = t + N / 2;
     if (u >= NL) u -= NL;
@@ -524,7 +528,7 @@ __device__ __noinline__ void det_rows_recomp(lf2* buf, const lf32* acc, gf2* __r
   auto st2 = [&](int line, int t, float2 v) {
     if (t < N) stv(Yr, line * N + t, cscale(v, ps));
   };
-  fft_lines<NL, true, RB, NT, LP, false>(buf, twL, ld2, st2);
+  fft_lines<NL, true, RB, 64, LP, false>(buf, twL, ld2, st2);
 }
 
 // Exact-ratio row pass: Psi[u][:] = cout (IFFT( FFT(cin Y[u][:]) hk ))[0:N],
@@ -539,7 +543,7 @@ __device__ __noinline__ void det_rows_fwd_czt(lf2* buf, lf32* acc, gf2* __restri
     return t < N ? cmul(ldv(Yr, line * N + t), ldv(tb, t)) : make_float2(0.f, 0.f);
   };
   auto st = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmul(v, ldv(tb, 2 * N + t))); };
-  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld, st);
+  fft_lines<NB, false, RB, 64, LP, false>(buf, twB, ld, st);
   auto ld2 = [&](int line, int t) { return ldv(buf, Ix::at(line, t)); };
   auto st2 = [&](int line, int t, float2 v) {
     if (t < N) {
@@ -548,7 +552,7 @@ __device__ __noinline__ void det_rows_fwd_czt(lf2* buf, lf32* acc, gf2* __restri
       acc[line * N + t] += cabs2(v);
     }
   };
-  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld2, st2);
+  fft_lines<NB, true, RB, 64, LP, false>(buf, twB, ld2, st2);
 }
 
 // Its adjoint: Z[u][:] = conj(cin) (IFFT( FFT(conj(cout) g2 Psi[u][:]) conj(hk) ))[0:N],
@@ -564,12 +568,12 @@ __device__ __noinline__ void det_rows_adj_czt(lf2* buf, const lf32* acc, gf2* __
                  : make_float2(0.f, 0.f);
   };
   auto st = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmulconj(ldv(tb, 2 * N + t), v)); };
-  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld, st);
+  fft_lines<NB, false, RB, 64, LP, false>(buf, twB, ld, st);
   auto ld2 = [&](int line, int t) { return ldv(buf, Ix::at(line, t)); };
   auto st2 = [&](int line, int t, float2 v) {
     if (t < N) stv(Yr, line * N + t, cmulconj(ldv(tb, t), v));
   };
-  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld2, st2);
+  fft_lines<NB, true, RB, 64, LP, false>(buf, twB, ld2, st2);
 }
 
 // Exact-ratio adjoint row pass that also returns this thread's share of the
@@ -592,17 +596,17 @@ __device__ __noinline__ float det_rows_adj_czt_ratio(lf2* buf, lf2* psi, const l
   auto ld_y = [&](int line, int t) {
     return t < N ? cmul(ldv(Yr, line * N + t), ldv(tb, t)) : make_float2(0.f, 0.f);
   };
-  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_y, st_h);
+  fft_lines<NB, false, RB, 64, LP, false>(buf, twB, ld_y, st_h);
   auto st_psi = [&](int line, int t, float2 v) {
     if (t < N) stv(psi, line * N + t, cmul(v, ldv(tb, N + t)));
   };
-  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_psi);
+  fft_lines<NB, true, RB, 64, LP, false>(buf, twB, ld_b, st_psi);
   // Psi_s and the terms
   auto ld_sy = [&](int line, int t) {
     return t < N ? cscale(cmul(ldv(Yr, line * N + t), ldv(tb, t)), static_cast<float>(t))
                  : make_float2(0.f, 0.f);
   };
-  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_sy, st_h);
+  fft_lines<NB, false, RB, 64, LP, false>(buf, twB, ld_sy, st_h);
   float ta = 0.f, tc = 0.f;
   auto st_terms = [&](int line, int t, float2 v) {
     if (t < N) {
@@ -614,18 +618,18 @@ __device__ __noinline__ float det_rows_adj_czt_ratio(lf2* buf, lf2* psi, const l
       tc += static_cast<float>(t - N / 2) * (G.y * ps.x - G.x * ps.y);
     }
   };
-  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_terms);
+  fft_lines<NB, true, RB, 64, LP, false>(buf, twB, ld_b, st_terms);
   // Z = F_x^H G over Y
   auto ld_g = [&](int line, int t) {
     return t < N ? cmulconj(ldv(tb, N + t), cscale(ldv(psi, line * N + t), acc[line * N + t]))
                  : make_float2(0.f, 0.f);
   };
   auto st_hc = [&](int line, int t, float2 v) { stv(buf, Ix::at(line, t), cmulconj(ldv(tb, 2 * N + t), v)); };
-  fft_lines<NB, false, RB, NT, LP, false>(buf, twB, ld_g, st_hc);
+  fft_lines<NB, false, RB, 64, LP, false>(buf, twB, ld_g, st_hc);
   auto st_z = [&](int line, int t, float2 v) {
     if (t < N) stv(Yr, line * N + t, cmulconj(ldv(tb, t), v));
   };
-  fft_lines<NB, true, RB, NT, LP, false>(buf, twB, ld_b, st_z);
+  fft_lines<NB, true, RB, 64, LP, false>(buf, twB, ld_b, st_z);
   return c2 * tc - inv_a * ta;
 }
 
@@ -650,13 +654,25 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
   __shared__ float2 psi[VAR == 2 ? RB * N : 1];
   // exact-ratio wavelength whose alpha-derivative this call computes
   auto ratio_l = [&](int l) { return VAR == 2 && jb.g_ratio != nullptr && jb.czt[l] != nullptr; };
-  const int c = r.u, k = la.iter * jb.C + c, u0 = r.sub * RB;
-  const int tid = threadIdx.x;
+  const int c = r.u, k = la.iter * jb.C + c;
+  // Each wave owns RW of the block's RB rows: their transforms, intensities,
+  // loss derivatives and adjoint rows; the waves meet only in the block sums.
+  constexpr int RW = RB / (NT / 64);
+  static_assert(RB % (NT / 64) == 0, "whole rows per wave");
+  const int wv = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+  const int u0 = r.sub * RB + wv * RW;  // first row of this wave
+  lf2* const bufw = (lf2*)buf + wv * RW * LPMAX;
+  lf32* const accw = (lf32*)acc + wv * RW * N;
+  lf2* const psiw = (lf2*)psi + (VAR == 2 ? wv * RW * N : 0);
   const size_t plane = static_cast<size_t>(N) * N;
+  auto wave_fence = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
 
   if (MODE != 2) {
-    for (int e = tid; e < RB * N; e += NT) acc[e] = 0.f;
-    __syncthreads();
+    for (int e = lane; e < RW * N; e += 64) accw[e] = 0.f;
+    wave_fence();
     for (int l = 0; l < jb.L; ++l) {
       const float ps = jb.pad_scale[l];
       const float2* twL = jb.tw_pad[l];
@@ -672,18 +688,18 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
         pad_switch(nl, [&](auto nlc) {
           constexpr int NL = decltype(nlc)::value;
           if constexpr (NL == czt_nb<N>())
-            det_rows_fwd_czt<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]), keep);
+            det_rows_fwd_czt<N, NL, RW>(bufw, accw, Yr, gmem(twL), gmem(jb.czt[l]), keep);
           else
-            det_rows_fwd<N, NL, RB>((lf2*)buf, (lf32*)acc, Yr, gmem(twL), ps, keep);
+            det_rows_fwd<N, NL, RW>(bufw, accw, Yr, gmem(twL), ps, keep);
         }, Rows{});
       }
     }
-    // acc = sum_{l,m} |Psi|^2 for RB rows
+    // acc = sum_{l,m} |Psi|^2 for this wave's rows
     float lsum = 0.f;
-    for (int e = tid; e < RB * N; e += NT) {
+    for (int e = lane; e < RW * N; e += 64) {
       const int line = e / N, x = e % N;
       const int pix = (u0 + line) * N + x;
-      float I = acc[e];
+      float I = accw[e];
       if (jb.background) I += gmem(jb.background)[pix];
       if (MODE == 1) {
         // I + B to the resampling buffer, or the final forward output
@@ -712,21 +728,22 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
         dell = meas;
       }
       lsum += wt * ell;
-      acc[e] = loss.gscale * wt * dell;  // 2 * scale * w * dloss/dI
+      accw[e] = loss.gscale * wt * dell;  // 2 * scale * w * dloss/dI
       // background gradient terms, summed over positions by k_bg_reduce
       if (MODE == 0 && jb.g_background)
-        gmem(reinterpret_cast<float*>(jb.GX))[static_cast<size_t>(c) * plane + pix] = acc[e];
+        gmem(reinterpret_cast<float*>(jb.GX))[static_cast<size_t>(c) * plane + pix] = accw[e];
     }
     if (MODE == 1) return;
+    wave_fence();
     const float s = block_sum(lsum, red);
-    if (tid == 0) gmem(jb.loss_part)[static_cast<size_t>(c) * (N / RB) + r.sub] = s;
+    if (threadIdx.x == 0) gmem(jb.loss_part)[static_cast<size_t>(c) * (N / RB) + r.sub] = s;
     if (MODE == 3) return;
   } else {
-    for (int e = tid; e < RB * N; e += NT) {
+    for (int e = lane; e < RW * N; e += 64) {
       const int line = e / N, x = e % N;
-      acc[e] = gmem(jb.ibuf)[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
+      accw[e] = gmem(jb.ibuf)[static_cast<size_t>(c) * plane + (u0 + line) * N + x];
     }
-    __syncthreads();
+    wave_fence();
   }
   for (int l = 0; l < jb.L; ++l) {
     const float ps = jb.pad_scale[l];
@@ -742,14 +759,14 @@ __global__ __launch_bounds__(NT) void k_det(Launch la, LossDev loss, bool spill)
         if constexpr (NL == czt_nb<N>()) {
           if (VAR == 2 && rl) {
             const double a = jb.czt_alpha[l];
-            da += det_rows_adj_czt_ratio<N, NL, RB>(
-                (lf2*)buf, (lf2*)psi, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]),
+            da += det_rows_adj_czt_ratio<N, NL, RW>(
+                bufw, psiw, accw, Yr, gmem(twL), gmem(jb.czt[l]),
                 static_cast<float>(1.0 / a), static_cast<float>(2.0 * kPi / (a * a)));
           } else {
-            det_rows_adj_czt<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), gmem(jb.czt[l]));
+            det_rows_adj_czt<N, NL, RW>(bufw, accw, Yr, gmem(twL), gmem(jb.czt[l]));
           }
         } else {
-          det_rows_recomp<N, NL, RB>((lf2*)buf, (const lf32*)acc, Yr, gmem(twL), ps);
+          det_rows_recomp<N, NL, RW>(bufw, accw, Yr, gmem(twL), ps);
         }
       }, Rows{});
     }

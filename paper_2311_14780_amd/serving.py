@@ -69,7 +69,9 @@ class JobRecord:
     admitted_at: float = math.nan
     finished_at: float = math.nan
     iters_done: int = 0
-    iter_latency: list = field(default_factory=list)   # seconds per iteration
+    iter_latency: list = field(default_factory=list)   # device seconds of each iteration's call
+    iter_wall: list = field(default_factory=list)      # wall seconds from the previous
+                                                       # completion (or admission) to this one
     losses: list = field(default_factory=list)
     reason: str = ""
 
@@ -88,8 +90,12 @@ class ServeReport:
     def _lat(self):
         return np.array([x for r in self.records.values() for x in r.iter_latency])
 
+    def _wall(self):
+        return np.array([x for r in self.records.values() for x in r.iter_wall])
+
     def summary(self) -> dict:
         it = self._lat()
+        wall = self._wall()
         done = [r for r in self.records.values() if r.status == "done"]
         jl = np.array([r.finished_at - r.arrival for r in done])
         q = lambda a, p: float(np.percentile(a, p)) if a.size else math.nan
@@ -103,6 +109,8 @@ class ServeReport:
             if self.makespan > 0 else math.nan,
             "iter_latency_p50_ms": round(1e3 * q(it, 50), 3),
             "iter_latency_p99_ms": round(1e3 * q(it, 99), 3),
+            "iter_wall_p50_ms": round(1e3 * q(wall, 50), 3),
+            "iter_wall_p99_ms": round(1e3 * q(wall, 99), 3),
             "job_latency_p50_s": round(q(jl, 50), 4),
             "job_latency_p99_s": round(q(jl, 99), 4),
             "ticks": self.ticks,
@@ -166,7 +174,13 @@ class Scheduler:
     * ``"hybrid"`` (default): the job that arrived first always runs, and
       the others fill up to ``tick_cap`` pattern-pixels of extra work,
       shortest remaining work first.  The oldest job thus progresses as
-      under first-come first-served while short jobs ride along.
+      under first-come first-served while short jobs ride along.  With
+      ``work_ratio`` set, a job rides along only if its work per iteration
+      is within that factor of the oldest job's, and the extra work of a
+      call is at most the oldest job's own: a call then takes at most about
+      twice the time of each of its jobs alone, so no job's iteration waits
+      for a much larger one (the iteration-latency bound), while the others
+      keep their arrival order for the next calls.
     * ``"srpt"``: shortest remaining work first, ``tick_cap`` in total.
     * ``"fifo"``: arrival order, ``tick_cap`` in total.
 
@@ -181,7 +195,8 @@ class Scheduler:
                  sleep: Callable[[float], None] = time.sleep,
                  on_tick: Optional[Callable[["Scheduler", int], None]] = None,
                  log: Optional[Callable[[str], None]] = None,
-                 tick_cap: Optional[int] = None, policy: str = "hybrid", depth: int = 1):
+                 tick_cap: Optional[int] = None, policy: str = "hybrid", depth: int = 1,
+                 work_ratio: Optional[float] = None):
         if policy not in POLICIES:
             raise ValueError(policy)
         if depth < 1:
@@ -189,6 +204,9 @@ class Scheduler:
         self.ex = executor
         self.budget = int(budget_bytes)
         self.tick_cap = tick_cap   # pattern-pixels per fused call (None: no cap)
+        if work_ratio is not None and not work_ratio >= 1.0:
+            raise ValueError("work_ratio must be at least 1")
+        self.work_ratio = work_ratio  # hybrid: riders within this factor of the head's work
         self.policy = policy
         self.depth = depth
         self.clock = clock
@@ -208,7 +226,13 @@ class Scheduler:
             cand = sorted(cand, key=lambda rh: (rh[0].arrival, rh[0].job_id))
             head, rest = cand[0], sorted(cand[1:], key=lambda rh: (rem(rh[0]), rh[0].arrival))
             sel, extra = [head], 0
+            ratio = self.work_ratio
+            hw = head[0].work
+            if ratio is not None:
+                cap = hw if cap is None else min(cap, hw)
             for r, h in rest:
+                if ratio is not None and not (hw / ratio <= r.work <= hw * ratio):
+                    continue
                 if cap is None or extra + r.work <= cap:
                     sel.append((r, h))
                     extra += r.work
@@ -234,6 +258,7 @@ class Scheduler:
         # admitted jobs: job_id -> [request, handle, launched, in flight, stop status]
         active: dict = {}
         inflight = deque()         # (ticket, job ids)
+        last_done: dict = {}       # job_id -> time of its last completed iteration
         used = peak = ticks = max_active = max_fused = pm = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
@@ -294,6 +319,7 @@ class Scheduler:
                 peak = max(peak, used)
                 recs[r.job_id].status = "running"
                 recs[r.job_id].admitted_at = now()
+                last_done[r.job_id] = recs[r.job_id].admitted_at
                 active[r.job_id] = [r, h, 0, 0, None]
             max_active = max(max_active, len(active))
             # enqueue a tick if there is room in the pipeline
@@ -313,11 +339,14 @@ class Scheduler:
                 ticket, jids = inflight.popleft()
                 losses, dt = self.ex.collect(ticket)
                 ticks += 1
+                t_done = now()
                 for jid, lo in zip(jids, losses):
                     a = active[jid]
                     rec = recs[jid]
                     a[3] -= 1
                     rec.iter_latency.append(dt)
+                    rec.iter_wall.append(t_done - last_done[jid])
+                    last_done[jid] = t_done
                     rec.losses.append(float(lo))
                     rec.iters_done += 1
                     pm += a[0].pattern_modes
@@ -539,12 +568,15 @@ def measure_service_times(executor: TorchExecutor, reqs, reps: int = 1) -> list:
 
 # Default work per fused call: two 256^2 x 4800-pattern-mode iterations.
 DEFAULT_TICK_CAP = 2 * 4800 * 256 * 256
+# Default fusion window of the hybrid policy: riders within 4x of the head's work.
+DEFAULT_WORK_RATIO = 4.0
 
 
 def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2.0,
                budget_bytes: Optional[int] = None, workspace_bytes: int = 8 << 30,
                device="cuda:0", log=print, tick_cap: Optional[int] = DEFAULT_TICK_CAP,
-               policy: str = "hybrid", depth: int = 2, exact_fraction: float = 0.0) -> dict:
+               policy: str = "hybrid", depth: int = 2, exact_fraction: float = 0.0,
+               work_ratio: Optional[float] = DEFAULT_WORK_RATIO) -> dict:
     """The serving stream end to end: job mix, data, service-time probe,
     Poisson arrivals at ``load`` times the sequential service rate, then the
     continuous-batching run and the first-come first-served sequential run
@@ -576,11 +608,12 @@ def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2
     out = {"jobs": n_jobs, "iters": iters, "seed": seed, "offered_load": load,
            "mean_arrival_gap_s": round(gap, 5), "budget_bytes": int(budget_bytes),
            "workspace_bytes": int(workspace_bytes), "tick_cap_pattern_pixels": tick_cap,
-           "policy": policy, "pipeline_depth": depth,
+           "policy": policy, "pipeline_depth": depth, "work_ratio": work_ratio,
            "exact_ratio_jobs": int(sum(w.exact_ratio for w in wl)),
            "pattern_modes_total": int(iters * sum(r.pattern_modes for r in reqs))}
     for mode in ("batch", "sequential"):
-        sch = Scheduler(ex, budget_bytes, log=log, tick_cap=tick_cap, policy=policy, depth=depth)
+        sch = Scheduler(ex, budget_bytes, log=log, tick_cap=tick_cap, policy=policy, depth=depth,
+                        work_ratio=work_ratio)
         rep = sch.run(reqs, mode)
         out[mode] = rep.summary()
         log(f"{mode}: {json_line(out[mode])}")
@@ -608,11 +641,15 @@ if __name__ == "__main__":
     ap.add_argument("--depth", type=int, default=2, help="fused calls in flight")
     ap.add_argument("--exact-fraction", type=float, default=0.0,
                     help="fraction of jobs using the exact-ratio propagator")
+    ap.add_argument("--work-ratio", type=float, default=DEFAULT_WORK_RATIO,
+                    help="hybrid policy: riders within this factor of the oldest job's work "
+                         "per iteration (0: no bound)")
     a = ap.parse_args()
     res = run_stream(a.jobs, a.iters, a.seed, a.load,
                      None if a.budget_gb <= 0 else int(a.budget_gb * 1e9),
                      int(a.workspace_gb * (1 << 30)),
                      log=lambda s: print(s, flush=True),
                      tick_cap=int(a.tick_cap) if a.tick_cap > 0 else None, policy=a.policy,
-                     depth=a.depth, exact_fraction=a.exact_fraction)
+                     depth=a.depth, exact_fraction=a.exact_fraction,
+                     work_ratio=a.work_ratio if a.work_ratio > 0 else None)
     print(json.dumps(res), flush=True)

@@ -257,3 +257,48 @@ def test_failure_is_noticed_one_tick_late_when_pipelined():
     assert r[1].status == "failed" and 3 <= r[1].iters_done <= 4
     assert r[0].status == "done" and r[0].iters_done == 8
     assert not ex.resident
+
+
+def reqk(i, arrival, K, iters=3, fp=1):
+    # work per iteration K L M N^2 (scheduler) and the fake executor's cost agree up to a scale
+    return JobRequest(job_id=i, arrival=arrival, iters=iters, K=K, L=1, M=1, N=128, H=256,
+                      W=256, pads=(128,), payload={"fp": fp, "work": K / 100.0})
+
+
+def test_work_ratio_keeps_much_smaller_jobs_out_of_a_large_jobs_call():
+    # head: 1000 positions; a 900-position job rides along (within 2x, fits the
+    # head's own work as extra), a 100-position job does not
+    reqs = [reqk(0, 0.0, 1000), reqk(1, 0.0, 900), reqk(2, 0.0, 100)]
+    _, ex, rep = run(reqs, budget=10, sched=dict(work_ratio=2.0))
+    assert ex.calls[0] == [0, 1]
+    assert all(not (0 in c and 2 in c) for c in ex.calls)
+    assert all(r.status == "done" for r in rep.records.values())
+    # without the bound the small job rides along with the head
+    _, ex2, _ = run(reqs, budget=10)
+    assert 2 in ex2.calls[0]
+
+
+def test_work_ratio_caps_the_extra_work_at_the_heads_own():
+    # three equal jobs: only one rider per call (extra work <= the head's)
+    reqs = [reqk(i, 0.0, 500) for i in range(3)]
+    _, ex, _ = run(reqs, budget=10, sched=dict(work_ratio=4.0))
+    assert all(len(c) <= 2 for c in ex.calls)
+
+
+def test_wall_latency_counts_the_ticks_a_job_waits():
+    # job 1 waits out job 0's calls while it is kept out of them
+    reqs = [reqk(0, 0.0, 1000, iters=2), reqk(1, 0.0, 100, iters=2)]
+    _, ex, rep = run(reqs, budget=10, sched=dict(work_ratio=2.0), overhead=0.0)
+    r0, r1 = rep.records[0], rep.records[1]
+    assert [c for c in ex.calls] == [[0], [0], [1], [1]]
+    # (iter_latency holds the executor's own timing: here the fake's host time)
+    np.testing.assert_allclose(r0.iter_wall, [10.0, 10.0])
+    # job 1's first iteration completes 21 s after its admission (it waited 20 s)
+    np.testing.assert_allclose(r1.iter_wall, [21.0, 1.0])
+    s = rep.summary()
+    assert s["iter_wall_p99_ms"] >= 1e3 * 20.0
+
+
+def test_work_ratio_below_one_is_rejected():
+    with pytest.raises(ValueError):
+        Scheduler(None, 1, work_ratio=0.5)
