@@ -14,7 +14,9 @@ Poisson draws from the model's own forward pass of the ground truth.
 Prints one JSON line.  The headline workload is the largest single-GPU
 configuration (C3: 5 wavelengths x 8 probe modes, 512 x 512 probe, 3072 x 3072
 object per wavelength, 2500 positions); ``extra`` holds the same figures for
-the four-wavelength 256 x 256 workload (C2).  ``value`` is pattern-modes per
+the four-wavelength 256 x 256 workload (C2), the reflection workload with the
+tilt table (C5) and the single-wavelength 64 x 64 case (C1, whose
+``ms_per_step`` is the latency of one loss + gradient + Adam step).  ``value`` is pattern-modes per
 second (one pattern-mode is one (position, wavelength, probe mode)
 propagation, forward and adjoint).
 ``roofline`` reports the kernel class with the largest GPU time: algorithmic
@@ -458,9 +460,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="C3",
                     help="workload of the headline line (default C3, the largest "
                          "single-GPU configuration)")
-    ap.add_argument("--extra", default="C2",
+    ap.add_argument("--extra", default="C2,C5,C1",
                     help="comma-separated workloads also timed and reported under 'extra' "
-                         "(default C2; empty for none)")
+                         "(default C2, C5 and C1, whose ms_per_step is the latency of the "
+                         "small single-wavelength case; empty for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
