@@ -324,8 +324,13 @@ struct Plan;  // Plan<n>::type = Radices<...>, product n
   };
 
 // Lengths that are multiples of 16 use the skewed row layout (see Lds) and
-// power-of-two radices first; the others start with an odd radix, so that the
-// strided writes of the first pass do not pile onto a few LDS banks.
+// power-of-two radices first; most others start with an odd radix, so that the
+// strided writes of the first pass do not pile onto a few LDS banks.  420, 600,
+// 675 and 750 instead take the order with the fewest butterfly instructions per
+// line when one wave transforms a line on its own (the detector kernel, which
+// is bound by vector-ALU issue there): 750 as 10 x 15 x 5 needs 635 wave
+// instructions per line against 717 for 5 x 15 x 10 (5 harmonics x 8 modes,
+// N = 512: detector kernel 172.7 -> 166.3 ms, column forward 80.9 -> 79.3 ms).
 PTYCHO_PLAN(64, 8, 8)
 PTYCHO_PLAN(72, 9, 8)
 PTYCHO_PLAN(80, 16, 5)
@@ -349,13 +354,13 @@ PTYCHO_PLAN(336, 16, 3, 7)
 PTYCHO_PLAN(343, 7, 7, 7)
 PTYCHO_PLAN(375, 15, 5, 5)
 PTYCHO_PLAN(384, 16, 8, 3)
-PTYCHO_PLAN(420, 7, 5, 12)
+PTYCHO_PLAN(420, 12, 5, 7)
 PTYCHO_PLAN(480, 16, 6, 5)
 PTYCHO_PLAN(512, 8, 8, 8)
 PTYCHO_PLAN(560, 16, 5, 7)
-PTYCHO_PLAN(600, 5, 12, 10)
-PTYCHO_PLAN(675, 9, 15, 5)
-PTYCHO_PLAN(750, 5, 15, 10)
+PTYCHO_PLAN(600, 12, 10, 5)
+PTYCHO_PLAN(675, 15, 15, 3)
+PTYCHO_PLAN(750, 10, 15, 5)
 // Bluestein lengths 2N of the exact-ratio propagator (N = 384, 512)
 PTYCHO_PLAN(768, 16, 16, 3)
 PTYCHO_PLAN(1024, 16, 16, 4)
