@@ -304,7 +304,8 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
 // most one segment per (job, selector) and launch, so the bound follows from
 // the selectors each phase enumerates:
 //  - a chunk iteration: 5 per slot (row forward, column forward, column
-//    adjoint, row adjoint, object gather), one per wavelength (probe
+//    adjoint (the plain or the paired launch, never both for one job), row
+//    adjoint, object gather), one per wavelength (probe
 //    reduction) and one each for ramps, detector, background sum, finalise;
 //  - the prologue: one per gradient output (kVars + distance ratio), status,
 //    window check, and one chirp table per wavelength;
@@ -378,6 +379,9 @@ int job_probe_group(const ptycho_job_t& j, bool want_probe) {
   if (!want_probe) return 1;
   int g = probe_group_of(j.N, j.M, eff_pad(j, 0));
   for (int l = 1; l < j.L; ++l) g = std::min(g, probe_group_of(j.N, j.M, eff_pad(j, l)));
+  if (g == 2)  // pairs run the paired instance on every wavelength
+    for (int l = 0; l < j.L; ++l)
+      if (!pair_capable(j.N, eff_pad(j, l))) return 1;
   return g;
 }
 
@@ -703,7 +707,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         nls.push_back(eff_pad(c.jobs[i], l));
   }
   // work units below run over slots (wavelength x sample mode)
-  std::vector<Phase::Item> colf(nls.size()), cola(nls.size());
+  std::vector<Phase::Item> colf(nls.size()), cola(nls.size()), colp(nls.size());
   for (size_t p = 0; p < nls.size(); ++p) {
     colf[p] = ph.begin();
     for (size_t q = 0; q < members.size(); ++q)
@@ -714,13 +718,18 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
   for (size_t q = 0; q < members.size(); ++q) ph.add(det, members[q], 0, cnt[q]);
   Phase::Item prob = ph.begin(), rowa = ph.begin(), obj = ph.begin();
   if (key.adjoint) {
+    // jobs with probe-gradient pairs run the paired instance (its own launch)
     for (size_t p = 0; p < nls.size(); ++p) {
-      cola[p] = ph.begin();
-      for (size_t q = 0; q < members.size(); ++q) {
-        const int pg = c.pgroup[members[q]];
-        for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l)
-          if (eff_pad_slot(c.jobs[members[q]], l) == nls[p])
-            ph.add(cola[p], members[q], l, (cnt[q] + pg - 1) / pg);
+      for (int pass = 0; pass < 2; ++pass) {
+        Phase::Item& it = pass == 0 ? cola[p] : colp[p];
+        it = ph.begin();
+        for (size_t q = 0; q < members.size(); ++q) {
+          const int pg = c.pgroup[members[q]];
+          if ((pg == 2) != (pass == 1)) continue;
+          for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l)
+            if (eff_pad_slot(c.jobs[members[q]], l) == nls[p])
+              ph.add(it, members[q], l, (cnt[q] + pg - 1) / pg);
+        }
       }
     }
     prob = ph.begin();
@@ -786,11 +795,13 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         bool uses = false;
         for (int l = 0; l < j.L; ++l) uses |= eff_pad(j, l) == nls[p];
         if (!uses || !cnt[q]) continue;
+        if (c.pgroup[members[q]] == 2) continue;  // paired launch below
         grouped |= c.pgroup[members[q]] > 1;
         lds = std::max(lds, col_adj_lds_of(N, nls[p], j.M, c.pgroup[members[q]]));
       }
       LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
                                         grouped, key.ratio_grad, s));
+      LAUNCH(KC_COL_ADJ, launch_col_adj_pair(N, nls[p], launch_of(c, colp[p], iter), colp[p].units, s));
     }
     LAUNCH(KC_PROBE_REDUCE, launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
     LAUNCH(KC_ROW_ADJ, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));

@@ -1068,6 +1068,160 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   }
 }
 
+// Column adjoint over pairs of consecutive positions: the probe-gradient
+// groups of two of jobs whose [M][N][G] LDS accumulator does not fit (many
+// modes at N = 512).  The modes are the outer loop: for mode m the block
+// transforms both positions' columns and adds their probe-gradient terms in
+// registers, in ascending position order, and writes the sum once, into the
+// first position's slot.  So the probe columns of a mode are read once per
+// pair, and the terms that the column adjoint writes and the probe reduction
+// reads halve.  Per position the arithmetic is that of k_col_adj (the same
+// transforms and products), and the pair's sum t0 + t1 is the value that a
+// two-position LDS group forms.  Ohat of both positions waits in LDS
+// (dynamic, [2][N][G]) until the y-shift adjoint at the end; the shifted
+// patches and the gradients go_p stay in registers.
+// units: (l, pair of positions) for the wavelengths whose DFT size is NL.
+template <int N, int NL>
+__global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Launch la) {
+  static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
+  constexpr int G = col_group_adj(N, NL);
+  constexpr int AT = col_adj_threads(N, NL);
+  constexpr int LP = G + 1;
+  constexpr int NE = N * G / AT;
+  const UnitRef r = decode_cols<N / G>(la);
+  const JobDev& jb = *r.jb;
+  if (*gmem(jb.status)) return;
+  __shared__ float2 buf[NL * LP];
+  __shared__ float red[AT / 64];
+  extern __shared__ float2 ohs[];  // [2][N * G], element e of this thread at e = tid + q AT
+  const int l = r.l, x0 = r.sub * G;
+  const int tid = threadIdx.x;
+  const int c0 = r.u * 2;
+  const int np = min(2, min(jb.C, jb.K - la.iter * jb.C) - c0);  // 1 or 2
+  const bool want_probe = jb.g_probe != nullptr;
+  const float2* __restrict__ twN = jb.tw_N;
+  const float2* __restrict__ twL = jb.tw_pad[l];
+  const float ps = jb.pad_scale[l];
+  const size_t plane = static_cast<size_t>(N) * N;
+  constexpr float invN = 1.0f / N;
+  auto ld_buf = [&](int line, int i) { return buf[i * LP + line]; };
+  auto st_buf = [&](int line, int i, float2 v) { buf[i * LP + line] = v; };
+  float2 o[2][NE], go[2][NE];
+  float sig[2], sgsum[2] = {0.f, 0.f};
+
+  // recompute Ohat = ramp_y FFT_y(X) (to LDS) and Osh = IFFT_y(Ohat) / N
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p < np) {
+      const int c = c0 + p, k = la.iter * jb.C + c;
+      const gf2* __restrict__ X = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * plane + x0;
+      const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
+      sig[p] = jb.sigma ? gmem(jb.sigma)[k] : 1.0f;
+      auto ld_x = [&](int line, int i) { return ldv(X, i * N + line); };
+      auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ldv(ry, i)); };
+      fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_x, st_ramp);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * AT, line = e % G, i = e / G;
+        ohs[p * N * G + e] = buf[i * LP + line];
+      }
+      fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * AT, line = e % G, i = e / G;
+        o[p][q] = cscale(buf[i * LP + line], invN);
+        go[p][q] = make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+    }
+  }
+
+  // chi_{p,m} = crop(DFT^H(embed(Z_{p,m}))); go_p += sig_p conj(P_m) chi;
+  // probe term sum_p sig_p conj(Osh_p) chi
+  auto st_chi = [&](int line, int t, float2 v) {
+    if (t < N) buf[t * LP + line] = cscale(v, ps);
+  };
+  for (int m = 0; m < jb.M; ++m) {
+    const gf2* __restrict__ P =
+        gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * plane + x0;
+    float2 term[NE];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < np) {
+        gf2* __restrict__ Zm =
+            gmem(jb.Y) + ((static_cast<size_t>(c0 + p) * jb.L + l) * jb.M + m) * plane + x0;
+        auto ld_z = [&](int line, int t) {
+          int u = t + N / 2;
+          if (u >= NL) u -= NL;
+          return u < N ? ldv(Zm, u * N + line) : make_float2(0.f, 0.f);
+        };
+        fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_z, st_chi);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const int e = tid + q * AT, line = e % G, i = e / G;
+          const float2 chi = buf[i * LP + line];
+          const float2 pc = cmulconj(ldv(P, i * N + line), chi);  // conj(P) chi
+          go[p][q].x = fmaf(sig[p], pc.x, go[p][q].x);
+          go[p][q].y = fmaf(sig[p], pc.y, go[p][q].y);
+          sgsum[p] += pc.x * o[p][q].x + pc.y * o[p][q].y;
+          if (want_probe) {
+            const float2 t = cscale(cmulconj(o[p][q], chi), sig[p]);
+            term[q] = p == 0 ? t : cadd(term[q], t);
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (want_probe) {
+      gf2* __restrict__ Z0 =
+          gmem(jb.Y) + ((static_cast<size_t>(c0) * jb.L + l) * jb.M + m) * plane + x0;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * AT, line = e % G, i = e / G;
+        stv(Z0, i * N + line, term[q]);
+      }
+    }
+  }
+
+  // per position: sigma partial, Ghat = FFT_y(go) (y-position derivative),
+  // adjoint y-shift to GX
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p < np) {
+      const int c = c0 + p;
+      const size_t slot = (static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub;
+      {
+        const float s = block_sum<AT>(sgsum[p], red);
+        if (tid == 0) gmem(jb.sg_part)[slot] = s;
+      }
+      const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * AT, line = e % G, i = e / G;
+        buf[i * LP + line] = go[p][q];
+      }
+      __syncthreads();
+      fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
+      float dsum = 0.f;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * AT, line = e % G, i = e / G;
+        const float2 gh = buf[i * LP + line];
+        const float2 oh = ohs[p * N * G + e];
+        const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
+        dsum += nu * (gh.y * oh.x - gh.x * oh.y);
+        buf[i * LP + line] = cmul(gh, cconj(ldv(ry, i)));
+      }
+      __syncthreads();
+      gf2* __restrict__ GX = gmem(jb.GX) + (static_cast<size_t>(c) * jb.L + l) * plane + x0;
+      auto st_gx = [&](int line, int i, float2 v) { stv(GX, i * N + line, cscale(v, invN)); };
+      fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_gx);
+      const float s = block_sum<AT>(dsum, red);
+      if (tid == 0) gmem(jb.dy_part)[slot] = s * invN;
+    }
+  }
+}
+
 // ------------------------------------------- probe gradient: ordered k sum
 // g_probe[l][m][pix] += sum over position groups (ascending) and sample
 // modes n (ascending) of Y[first c of group][l Ns + n][m][pix]
@@ -1523,11 +1677,20 @@ constexpr int kProbeGroup = 4;
 // margin for the reduction scratch.
 constexpr size_t kColAdjLds = 156 * 1024;
 
+// Zero-padded DFT sizes of N >= 256 have a paired column-adjoint instance.
+bool pair_capable(int N, int nl) { return N >= 256 && nl != czt_len(N); }
+
 int probe_group_of(int N, int M, int nl) {
   const size_t G = static_cast<size_t>(col_group_adj(N, nl));
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
   const size_t buf = static_cast<size_t>(nl) * (G + 1) * sizeof(float2);
-  return acc + buf <= kColAdjLds ? kProbeGroup : 1;
+  if (acc + buf <= kColAdjLds) return kProbeGroup;
+  if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + buf <= kColAdjLds) return 2;
+  return 1;
+}
+
+size_t col_adj_pair_lds(int N, int nl) {
+  return 2 * static_cast<size_t>(N) * col_group_adj(N, nl) * sizeof(float2);
 }
 
 size_t col_adj_lds_of(int N, int nl, int M, int group) {
@@ -1653,6 +1816,31 @@ hipError_t launch_col_adj_inst(dim3 g, const Launch& la, size_t dyn_lds, bool gr
   }
   hipLaunchKernelGGL((k_col_adj<NN, NL, true, RATIO>), g, dim3(col_adj_threads(NN, NL)), dyn_lds, s, la);
   return hipGetLastError();
+}
+
+template <int NN, int NL>
+hipError_t launch_col_adj_pair_inst(dim3 g, const Launch& la, hipStream_t s) {
+  const size_t dyn = col_adj_pair_lds(NN, NL);
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col_adj_pair<NN, NL>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(dyn));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_col_adj_pair<NN, NL>), g, dim3(col_adj_threads(NN, NL)), dyn, s, la);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_adj_pair(int N, int nl, const Launch& la, long long units, hipStream_t s) {
+  if (units <= 0) return hipSuccess;
+  if (!pair_capable(N, nl)) return hipErrorInvalidValue;
+  return with_N(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    return host_pad(nl, [&](auto pc) {
+      constexpr int NL = decltype(pc)::value;
+      if constexpr (NN >= 256 && NL != czt_nb<NN>())
+        return launch_col_adj_pair_inst<NN, NL>(grid1(units * (NN / col_group_adj(NN, NL))), la, s);
+      return hipErrorInvalidValue;
+    }, ColList<NN>{});
+  });
 }
 
 hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
