@@ -44,6 +44,19 @@ __device__ __forceinline__ PTYCHO_GLOBAL T* gmem(T* p) { return (PTYCHO_GLOBAL T
 template <class T>
 __device__ __forceinline__ const PTYCHO_GLOBAL T* gmem(const T* p) { return (const PTYCHO_GLOBAL T*)p; }
 
+// A wave-uniform table pointer that the compiler cannot see through.  Loads
+// through it are not hoisted out of an enclosing loop, which would keep every
+// thread's loaded table values in registers across the whole loop.  The
+// table lives in global memory: the rebuilt pointer says so.
+template <class P>
+__device__ __forceinline__ const gf2* opaque_table(P p) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+  unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return reinterpret_cast<const gf2*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // Element access that works for generic float2 pointers and for the
 // address-space qualified vector pointers above.
 __device__ __forceinline__ float2 ldv(const float2* p, int i) { return p[i]; }
@@ -630,15 +643,9 @@ __device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const PassTw<n, R, 
 template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Buf, class Tw,
           class Load, class Store>
 __device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, const Store& store) {
-  // The twiddle base is made opaque here so that the compiler cannot hoist
-  // the (loop-invariant) twiddle loads of an FFT out of an enclosing loop,
-  // which would pin every twiddle value in registers for the whole loop.
-  // The table lives in global memory: the rebuilt pointer says so.
-  const unsigned long long a = reinterpret_cast<unsigned long long>(tw);
-  unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
-  unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
-  asm volatile("" : "+s"(lo), "+s"(hi));
-  const gf2* tg = reinterpret_cast<const gf2*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  // The twiddle base is made opaque so that the (loop-invariant) twiddle
+  // loads of an FFT stay inside any loop around the call.
+  const gf2* tg = opaque_table(tw);
   using Plan0 = typename Plan<n>::type;
   PassTw<n, FirstRadixOf<Plan0>::value, LINES, NT> w0;  // the first pass has no twiddles
   stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, w0, load, store, Plan0{});

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(CNT, col_fwd_waves(N, NL)) void k_col_fwd(Launch la
         gmem(jb.Y) + ((static_cast<size_t>(c) * jb.L + l) * jb.M + m) * N * N + x0;
     if constexpr (NL == czt_nb<N>()) {
       // exact ratio: cin psi -> FFT -> times the kernel DFT -> IFFT -> cout
-      const gf2* __restrict__ tb = gmem(jb.czt[l]);
+      const gf2* __restrict__ tb = opaque_table(jb.czt[l]);  // loads stay in the mode loop
       auto ld_c = [&](int line, int t) {
         return t < N ? cmul(buf[t * LP + line], ldv(tb, t)) : make_float2(0.f, 0.f);
       };
@@ -931,9 +931,9 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   const bool want_ratio = RATIO && jb.g_ratio != nullptr;
   // first-transform input of mode m at FFT index t: the cropped bins embedded
   // at their frequencies, or (exact ratio) conj(cout) Z in detector order
-  auto zin_at = [&](const gf2* __restrict__ Zm, int line, int t) {
+  auto zin_at = [&](const gf2* __restrict__ Zm, const gf2* __restrict__ tbm, int line, int t) {
     if constexpr (CZT) {
-      return t < N ? cmulconj(ldv(tb, N + t), ldv(Zm, t * N + line)) : make_float2(0.f, 0.f);
+      return t < N ? cmulconj(ldv(tbm, N + t), ldv(Zm, t * N + line)) : make_float2(0.f, 0.f);
     } else {
       int u = t + N / 2;
       if (u >= NL) u -= NL;
@@ -947,28 +947,34 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   using ZIn = PreIn<NL, G, AT, true>;
   auto zload = [&](int m, ZIn& zin) {
     const gf2* __restrict__ Zm = Z0 + static_cast<size_t>(m) * N * N;
-    fft_first_load(zin, [&](int line, int t) { return zin_at(Zm, line, t); });
+    fft_first_load(zin, [&](int line, int t) { return zin_at(Zm, tb, line, t); });
   };
   ZIn zcur;
   if constexpr (PREFETCH) zload(0, zcur);
+#pragma unroll 1
   for (int m = 0; m < jb.M; ++m) {
     gf2* __restrict__ Z = Z0 + static_cast<size_t>(m) * N * N;
     const gf2* __restrict__ P =
         gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * N * N + x0;
+    // the chirp table is read through a pointer the compiler cannot see
+    // through, so that its loads stay in the mode loop instead of every
+    // thread's table values being held in registers across it (exact ratio,
+    // N = 256: 72 spilled registers before)
+    const gf2* __restrict__ tbm = CZT ? opaque_table(tb) : nullptr;
     auto st_chi = [&](int line, int t, float2 v) {
       if (t < N) buf[t * LP + line] = cscale(v, ps);
     };
     // exact ratio: FFT, times conj(kernel DFT), IFFT, conj(cin)
-    auto st_hc = [&](int line, int t, float2 v) { buf[t * LP + line] = cmulconj(ldv(tb, 2 * N + t), v); };
+    auto st_hc = [&](int line, int t, float2 v) { buf[t * LP + line] = cmulconj(ldv(tbm, 2 * N + t), v); };
     auto ld_b = [&](int line, int t) { return buf[t * LP + line]; };
     auto st_chic = [&](int line, int t, float2 v) {
-      if (t < N) buf[t * LP + line] = cmulconj(ldv(tb, t), v);
+      if (t < N) buf[t * LP + line] = cmulconj(ldv(tbm, t), v);
     };
     if constexpr (RATIO) {
       if (want_ratio) {
         // y-axis term of dL/d alpha: chi_u = F_y^H (u Z), summed against r psi
         auto ld_u = [&](int line, int t) {
-          return cscale(zin_at(Z, line, t), static_cast<float>(t - N / 2));
+          return cscale(zin_at(Z, tbm, line, t), static_cast<float>(t - N / 2));
         };
         fft_lines<NL, false, G, AT, LP, true>(buf, twL, ld_u, st_hc);
         fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_b, st_chic);
@@ -983,7 +989,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
       }
     }
     if constexpr (!PREFETCH) {
-      auto ld_z = [&](int line, int t) { return zin_at(Z, line, t); };
+      auto ld_z = [&](int line, int t) { return zin_at(Z, tbm, line, t); };
       if constexpr (CZT) {
         fft_lines<NL, false, G, AT, LP, true>(buf, twL, ld_z, st_hc);
         fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_b, st_chic);
