@@ -90,12 +90,13 @@ class ServeReport:
     def _lat(self):
         return np.array([x for r in self.records.values() for x in r.iter_latency])
 
-    def _wall(self):
-        return np.array([x for r in self.records.values() for x in r.iter_wall])
+    def _wall(self, first: bool = True):
+        return np.array([x for r in self.records.values() for x in r.iter_wall[0 if first else 1:]])
 
     def summary(self) -> dict:
         it = self._lat()
         wall = self._wall()
+        gap = self._wall(first=False)  # between consecutive iterations only
         done = [r for r in self.records.values() if r.status == "done"]
         jl = np.array([r.finished_at - r.arrival for r in done])
         q = lambda a, p: float(np.percentile(a, p)) if a.size else math.nan
@@ -111,6 +112,8 @@ class ServeReport:
             "iter_latency_p99_ms": round(1e3 * q(it, 99), 3),
             "iter_wall_p50_ms": round(1e3 * q(wall, 50), 3),
             "iter_wall_p99_ms": round(1e3 * q(wall, 99), 3),
+            "iter_gap_p50_ms": round(1e3 * q(gap, 50), 3),
+            "iter_gap_p99_ms": round(1e3 * q(gap, 99), 3),
             "job_latency_p50_s": round(q(jl, 50), 4),
             "job_latency_p99_s": round(q(jl, 99), 4),
             "ticks": self.ticks,
@@ -338,9 +341,11 @@ class Scheduler:
             if inflight:
                 ticket, jids = inflight.popleft()
                 losses, dt = self.ex.collect(ticket)
+                # device seconds of each job's call (one figure: a single call)
+                dts = list(dt) if isinstance(dt, (list, tuple)) else [dt] * len(jids)
                 ticks += 1
                 t_done = now()
-                for jid, lo in zip(jids, losses):
+                for jid, lo, dt in zip(jids, losses, dts):
                     a = active[jid]
                     rec = recs[jid]
                     a[3] -= 1
@@ -396,12 +401,15 @@ class TorchExecutor(Executor):
     [L][M][N][N], ``pos`` float32 [K][2], ``measured`` float32 [K][N][N].
     """
 
-    def __init__(self, device, workspace_bytes: int, keep_final: bool = False):
+    def __init__(self, device, workspace_bytes: int, keep_final: bool = False,
+                 fuse_work: Optional[int] = None):
         import torch
         from . import binding as B
         self.torch = torch
         self.B = B
         self.device = torch.device(device)
+        # pattern-pixels up to which a tick's jobs share one call (None: all)
+        self.fuse_work = fuse_work
         self.ws = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=self.device)
         # job data is copied in on its own stream while other jobs compute
         self.copy_stream = torch.cuda.Stream(device=self.device)
@@ -456,6 +464,12 @@ class TorchExecutor(Executor):
                 h["ev"].synchronize()
                 return
 
+    def calls_of(self, handles) -> list:
+        """The tick's jobs split into calls: consecutive jobs share a call
+        while its work stays within ``fuse_work`` pattern-pixels; a larger
+        job gets a call of its own."""
+        return split_calls([h["req"].work for h in handles], self.fuse_work)
+
     def launch(self, handles):
         torch = self.torch
         main = torch.cuda.current_stream(self.device)
@@ -464,24 +478,31 @@ class TorchExecutor(Executor):
                 main.wait_event(h["ev"])  # the job's data is in place
                 h["waited"] = True
             h["adam"]["t"] += 1
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        start.record(main)
-        self.B.ptycho_step([h["prob"] for h in handles], [h["g"] for h in handles],
-                           [h["adam"] for h in handles], workspace=self.ws, stream=main)
-        end.record(main)
+        timed = []  # (start, end, number of jobs) per call, in job order
+        for idx in self.calls_of(handles):
+            hs = [handles[i] for i in idx]
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(main)
+            self.B.ptycho_step([h["prob"] for h in hs], [h["g"] for h in hs],
+                               [h["adam"] for h in hs], workspace=self.ws, stream=main)
+            end.record(main)
+            timed.append((start, end, len(hs)))
         # snapshot of this iteration's losses (the next call overwrites them)
         snap = torch.cat([h["g"]["loss"] for h in handles])
         host = torch.empty(len(handles), dtype=snap.dtype, pin_memory=True)
         host.copy_(snap, non_blocking=True)
         done = torch.cuda.Event()
         done.record(main)
-        return (start, end, done, host)
+        return (timed, done, host)
 
     def collect(self, ticket):
-        start, end, done, host = ticket
+        timed, done, host = ticket
         done.synchronize()
-        return [float(x) for x in host], start.elapsed_time(end) * 1e-3
+        dts = []
+        for start, end, n in timed:
+            dts += [start.elapsed_time(end) * 1e-3] * n
+        return [float(x) for x in host], dts
 
     def step(self, handles) -> list:
         return self.collect(self.launch(handles))[0]
@@ -566,17 +587,44 @@ def measure_service_times(executor: TorchExecutor, reqs, reps: int = 1) -> list:
     return out
 
 
-# Default work per fused call: two 256^2 x 4800-pattern-mode iterations.
-DEFAULT_TICK_CAP = 2 * 4800 * 256 * 256
-# Default fusion window of the hybrid policy: riders within 4x of the head's work.
-DEFAULT_WORK_RATIO = 4.0
+# Default extra work per tick of the hybrid policy: one 256^2 x 4800-pattern-
+# mode iteration.  On the 64-job stream below it keeps the job-latency p99 at
+# that of first-come first-served execution (twice as much shortens the
+# median further but lengthens the p99).
+DEFAULT_TICK_CAP = 4800 * 256 * 256
+# Default fusion window of the hybrid policy: none (every rider within the cap).
+DEFAULT_WORK_RATIO = None
+# Calls of fewer pattern-pixels than this are dominated by their ~25 kernel
+# launches (a 64^2 x 100-position single-mode step takes 0.12 ms against
+# about 0.01 ms of work at the rate of a saturated step), so jobs below it
+# share one call; larger jobs fill the GPU alone and run in calls of their
+# own, each taking its own time.
+DEFAULT_FUSE_WORK = 8 << 20
+
+
+def split_calls(works, fuse_work: Optional[int]) -> list:
+    """Indices of each call: consecutive jobs share a call while its summed
+    work stays within ``fuse_work`` (None: one call for all)."""
+    if fuse_work is None:
+        return [list(range(len(works)))]
+    calls, cur, acc = [], [], 0
+    for i, w in enumerate(works):
+        if cur and acc + w > fuse_work:
+            calls.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += w
+    if cur:
+        calls.append(cur)
+    return calls
 
 
 def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2.0,
                budget_bytes: Optional[int] = None, workspace_bytes: int = 8 << 30,
                device="cuda:0", log=print, tick_cap: Optional[int] = DEFAULT_TICK_CAP,
                policy: str = "hybrid", depth: int = 2, exact_fraction: float = 0.0,
-               work_ratio: Optional[float] = DEFAULT_WORK_RATIO) -> dict:
+               work_ratio: Optional[float] = DEFAULT_WORK_RATIO,
+               fuse_work: Optional[int] = DEFAULT_FUSE_WORK) -> dict:
     """The serving stream end to end: job mix, data, service-time probe,
     Poisson arrivals at ``load`` times the sequential service rate, then the
     continuous-batching run and the first-come first-served sequential run
@@ -587,7 +635,7 @@ def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2
     t0 = time.perf_counter()
     hosts = host_jobs(wl)
     log(f"host data of {n_jobs} jobs: {time.perf_counter() - t0:.1f} s")
-    ex = TorchExecutor(device, workspace_bytes)
+    ex = TorchExecutor(device, workspace_bytes, fuse_work=fuse_work)
     reqs = build_requests(wl, hosts, np.zeros(n_jobs), iters, device)
     del hosts
     log(f"measured patterns: {time.perf_counter() - t0:.1f} s")
@@ -609,6 +657,7 @@ def run_stream(n_jobs: int = 64, iters: int = 50, seed: int = 4, load: float = 2
            "mean_arrival_gap_s": round(gap, 5), "budget_bytes": int(budget_bytes),
            "workspace_bytes": int(workspace_bytes), "tick_cap_pattern_pixels": tick_cap,
            "policy": policy, "pipeline_depth": depth, "work_ratio": work_ratio,
+           "fuse_work_pattern_pixels": fuse_work,
            "exact_ratio_jobs": int(sum(w.exact_ratio for w in wl)),
            "pattern_modes_total": int(iters * sum(r.pattern_modes for r in reqs))}
     for mode in ("batch", "sequential"):
@@ -641,9 +690,12 @@ if __name__ == "__main__":
     ap.add_argument("--depth", type=int, default=2, help="fused calls in flight")
     ap.add_argument("--exact-fraction", type=float, default=0.0,
                     help="fraction of jobs using the exact-ratio propagator")
-    ap.add_argument("--work-ratio", type=float, default=DEFAULT_WORK_RATIO,
+    ap.add_argument("--work-ratio", type=float, default=DEFAULT_WORK_RATIO or 0.0,
                     help="hybrid policy: riders within this factor of the oldest job's work "
                          "per iteration (0: no bound)")
+    ap.add_argument("--fuse-work", type=float, default=DEFAULT_FUSE_WORK,
+                    help="pattern-pixels up to which a tick's jobs share one call; larger "
+                         "jobs run in calls of their own (0: one call per tick)")
     a = ap.parse_args()
     res = run_stream(a.jobs, a.iters, a.seed, a.load,
                      None if a.budget_gb <= 0 else int(a.budget_gb * 1e9),
@@ -651,5 +703,6 @@ if __name__ == "__main__":
                      log=lambda s: print(s, flush=True),
                      tick_cap=int(a.tick_cap) if a.tick_cap > 0 else None, policy=a.policy,
                      depth=a.depth, exact_fraction=a.exact_fraction,
-                     work_ratio=a.work_ratio if a.work_ratio > 0 else None)
+                     work_ratio=a.work_ratio if a.work_ratio > 0 else None,
+                     fuse_work=int(a.fuse_work) if a.fuse_work > 0 else None)
     print(json.dumps(res), flush=True)

@@ -108,6 +108,34 @@ def test_sequential_and_batched_runs_agree():
                 assert torch.equal(x, y), (policy, j)
 
 
+def test_ticks_split_into_calls_agree_with_sequential():
+    """Jobs above the fusion threshold run in calls of their own within a
+    tick (each timed on its own); the states are those of sequential runs."""
+    from paper_2311_14780_amd import serving as S
+    reqs = _requests(3)
+    for r in reqs:
+        r.arrival = 0.0
+    ex = S.TorchExecutor(DEV, 256 << 20, keep_final=True)
+    seq_rep = S.Scheduler(ex, 1 << 40).run(reqs, "sequential")
+    seq = dict(ex.final)
+    # threshold: jobs 1 and 2 (adjacent) fit one call, job 0 does not join them
+    fuse = reqs[1].work + reqs[2].work
+    assert reqs[0].work + reqs[1].work > fuse
+    split = S.TorchExecutor(DEV, 256 << 20, keep_final=True, fuse_work=fuse)
+    calls = split.calls_of([{"req": r} for r in reqs])
+    print("calls of one tick over all jobs:", calls, flush=True)
+    assert [1, 2] in calls and 1 < len(calls) < len(reqs)
+    rep = S.Scheduler(split, 1 << 40, tick_cap=None, policy="hybrid", depth=2).run(reqs, "batch")
+    assert rep.max_fused == len(reqs)
+    for j, a in seq.items():
+        assert rep.records[j].losses == seq_rep.records[j].losses, j
+        for x, y in zip(a, split.final[j]):
+            assert torch.equal(x, y), j
+    # each job's iteration latency is its own call's device time
+    lat = {j: r.iter_latency[0] for j, r in rep.records.items()}
+    assert len(set(lat.values())) > 1, lat
+
+
 def test_jobs_admitted_mid_flight_with_pipelined_ticks():
     """Real clock, two fused calls in flight, job data copied in on its own
     stream while earlier jobs compute: nothing fails and every job ends in

@@ -302,3 +302,31 @@ def test_wall_latency_counts_the_ticks_a_job_waits():
 def test_work_ratio_below_one_is_rejected():
     with pytest.raises(ValueError):
         Scheduler(None, 1, work_ratio=0.5)
+
+
+def test_split_calls_groups_consecutive_small_jobs():
+    from paper_2311_14780_amd.serving import split_calls
+    assert split_calls([5, 1, 1, 1, 9, 2], None) == [[0, 1, 2, 3, 4, 5]]
+    # small jobs share a call up to the threshold; a larger job runs alone
+    assert split_calls([1, 1, 1, 9, 2, 2], 3) == [[0, 1, 2], [3], [4], [5]]
+    assert split_calls([2, 2, 1], 4) == [[0, 1], [2]]
+    assert split_calls([], 4) == []
+
+
+class SplitExecutor(FakeExecutor):
+    """Reports each job's own device time, as an executor that runs the
+    jobs of a tick in calls of their own does."""
+
+    def launch(self, handles):
+        losses = self.step(handles)
+        return losses, [h.payload["work"] for h in handles]
+
+
+def test_per_job_device_times_are_recorded_per_job():
+    clk = Clock()
+    ex = SplitExecutor(clk, overhead=0.0)
+    reqs = [req(0, 0.0, 1, work=4.0, iters=2), req(1, 0.0, 1, work=1.0, iters=2)]
+    rep = Scheduler(ex, 10, clock=clk, sleep=clk.sleep).run(reqs, "batch")
+    assert ex.calls[0] == [0, 1]
+    assert rep.records[0].iter_latency == [4.0, 4.0]
+    assert rep.records[1].iter_latency == [1.0, 1.0]
