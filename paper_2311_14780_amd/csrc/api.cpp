@@ -638,6 +638,13 @@ struct Phase {
     ProfScope prof_scope_(cls, s, c.profile);  \
     if ((x) != hipSuccess) return PTYCHO_EHIP; \
   } while (0)
+// A launch over `units` work units: skipped, with its profiling events, when
+// there are none (the launchers enqueue nothing then), so that the profile
+// counts kernels that ran.
+#define LAUNCH_U(cls, units, x)     \
+  do {                              \
+    if ((units) > 0) LAUNCH(cls, x); \
+  } while (0)
 
 int upload_phase(const Call& c, const Phase& ph, hipStream_t s) {
   if (ph.segs.empty()) return PTYCHO_OK;
@@ -673,10 +680,10 @@ int run_prologue(Call& c, hipStream_t s) {
       if (is_czt(c.jobs[i], l)) ph.add(czt, i, l * ns_of(c.jobs[i]), czt_table_blocks(c.jobs[i].N));
   int e = upload_phase(c, ph, s);
   if (e) return e;
-  LAUNCH(KC_FILL, launch_simple(KZeroGrads, launch_of(c, zero, 0), zero.units, s));
-  LAUNCH(KC_PREP, launch_simple(KSetStatus, launch_of(c, stat, 0), stat.units, s));
-  LAUNCH(KC_PREP, launch_simple(KValidate, launch_of(c, val, 0), val.units, s));
-  LAUNCH(KC_PREP, launch_simple(KCztTables, launch_of(c, czt, 0), czt.units, s));
+  LAUNCH_U(KC_FILL, zero.units, launch_simple(KZeroGrads, launch_of(c, zero, 0), zero.units, s));
+  LAUNCH_U(KC_PREP, stat.units, launch_simple(KSetStatus, launch_of(c, stat, 0), stat.units, s));
+  LAUNCH_U(KC_PREP, val.units, launch_simple(KValidate, launch_of(c, val, 0), val.units, s));
+  LAUNCH_U(KC_PREP, czt.units, launch_simple(KCztTables, launch_of(c, czt, 0), czt.units, s));
   return PTYCHO_OK;
 }
 
@@ -764,29 +771,32 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
   int e = upload_phase(c, ph, s);
   if (e) return e;
 
-  LAUNCH(KC_PREP, launch_simple(KPrep, launch_of(c, prep, iter), prep.units, s));
-  LAUNCH(KC_ROW_FWD, launch_row_fwd(N, launch_of(c, rowf, iter), rowf.units, s));
+  LAUNCH_U(KC_PREP, prep.units, launch_simple(KPrep, launch_of(c, prep, iter), prep.units, s));
+  LAUNCH_U(KC_ROW_FWD, rowf.units, launch_row_fwd(N, launch_of(c, rowf, iter), rowf.units, s));
   for (size_t p = 0; p < nls.size(); ++p)
-    LAUNCH(KC_COL_FWD, launch_col_fwd(N, nls[p], launch_of(c, colf[p], iter), colf[p].units, s));
+    LAUNCH_U(KC_COL_FWD, colf[p].units,
+             launch_col_fwd(N, nls[p], launch_of(c, colf[p], iter), colf[p].units, s));
   const Launch ldet = launch_of(c, det, iter);
   if (c.which == 0) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, false, var, s));
-    if (key.resample) LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, true, s));
+    LAUNCH_U(KC_DET, det.units, launch_det(N, ldet, det.units, c.loss, 1, false, var, s));
+    if (key.resample)
+      LAUNCH_U(KC_RESAMPLE, det.units, launch_resample_loss(N, ldet, det.units, c.loss, true, s));
     return PTYCHO_OK;
   }
   if (!key.resample) {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, var, s));
+    LAUNCH_U(KC_DET, det.units,
+             launch_det(N, ldet, det.units, c.loss, key.adjoint ? 0 : 3, false, var, s));
   } else {
-    LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, var, s));
-    LAUNCH(KC_RESAMPLE, launch_resample_loss(N, ldet, det.units, c.loss, false, s));
+    LAUNCH_U(KC_DET, det.units, launch_det(N, ldet, det.units, c.loss, 1, key.adjoint, var, s));
+    LAUNCH_U(KC_RESAMPLE, det.units, launch_resample_loss(N, ldet, det.units, c.loss, false, s));
     if (key.adjoint) {
-      LAUNCH(KC_RESAMPLE, launch_resample_T(N, ldet, det.units, s));
-      LAUNCH(KC_DET, launch_det(N, ldet, det.units, c.loss, 2, false, var, s));
+      LAUNCH_U(KC_RESAMPLE, det.units, launch_resample_T(N, ldet, det.units, s));
+      LAUNCH_U(KC_DET, det.units, launch_det(N, ldet, det.units, c.loss, 2, false, var, s));
     }
   }
   if (key.adjoint) {
     // background gradient: before the column adjoint reuses GX
-    LAUNCH(KC_FINALIZE, launch_simple(KBgReduce, launch_of(c, bgr, iter), bgr.units, s));
+    LAUNCH_U(KC_FINALIZE, bgr.units, launch_simple(KBgReduce, launch_of(c, bgr, iter), bgr.units, s));
     for (size_t p = 0; p < nls.size(); ++p) {
       size_t lds = 0;  // the launch's largest probe-gradient accumulator
       bool grouped = false;
@@ -799,15 +809,18 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         grouped |= c.pgroup[members[q]] > 1;
         lds = std::max(lds, col_adj_lds_of(N, nls[p], j.M, c.pgroup[members[q]]));
       }
-      LAUNCH(KC_COL_ADJ, launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
-                                        grouped, key.ratio_grad, s));
-      LAUNCH(KC_COL_ADJ, launch_col_adj_pair(N, nls[p], launch_of(c, colp[p], iter), colp[p].units, s));
+      LAUNCH_U(KC_COL_ADJ, cola[p].units,
+               launch_col_adj(N, nls[p], launch_of(c, cola[p], iter), cola[p].units, lds,
+                              grouped, key.ratio_grad, s));
+      LAUNCH_U(KC_COL_ADJ, colp[p].units,
+               launch_col_adj_pair(N, nls[p], launch_of(c, colp[p], iter), colp[p].units, s));
     }
-    LAUNCH(KC_PROBE_REDUCE, launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
-    LAUNCH(KC_ROW_ADJ, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));
-    LAUNCH(KC_OBJ_GATHER, launch_simple(KObjGather, launch_of(c, obj, iter), obj.units, s));
+    LAUNCH_U(KC_PROBE_REDUCE, prob.units,
+             launch_simple(KProbeReduce, launch_of(c, prob, iter), prob.units, s));
+    LAUNCH_U(KC_ROW_ADJ, rowa.units, launch_row_adj(N, launch_of(c, rowa, iter), rowa.units, s));
+    LAUNCH_U(KC_OBJ_GATHER, obj.units, launch_simple(KObjGather, launch_of(c, obj, iter), obj.units, s));
   }
-  LAUNCH(KC_FINALIZE, launch_simple(KFinalize, launch_of(c, fin, iter), fin.units, s));
+  LAUNCH_U(KC_FINALIZE, fin.units, launch_simple(KFinalize, launch_of(c, fin, iter), fin.units, s));
   return PTYCHO_OK;
 }
 
@@ -832,9 +845,9 @@ int run_epilogue(Call& c, hipStream_t s) {
   }
   int e = upload_phase(c, ph, s);
   if (e) return e;
-  LAUNCH(KC_FINALIZE, launch_regulariser(launch_of(c, reg, 0), reg.units, c.loss, s));
-  LAUNCH(KC_FINALIZE, launch_loss_total(launch_of(c, tot, 0), tot.units, c.loss, c.scale, s));
-  LAUNCH(KC_ADAM, launch_simple(KAdam, launch_of(c, ad, 0), ad.units, s));
+  LAUNCH_U(KC_FINALIZE, reg.units, launch_regulariser(launch_of(c, reg, 0), reg.units, c.loss, s));
+  LAUNCH_U(KC_FINALIZE, tot.units, launch_loss_total(launch_of(c, tot, 0), tot.units, c.loss, c.scale, s));
+  LAUNCH_U(KC_ADAM, ad.units, launch_simple(KAdam, launch_of(c, ad, 0), ad.units, s));
   return PTYCHO_OK;
 }
 

@@ -388,11 +388,15 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
 // ---------------------------------------------------------- column forward
 // Osh = y-shift of X columns; Y_m = (1/sqrt(NL)) crop( DFT_NL_y( sigma P_m Osh ) )
 // units: (l, c) for the wavelengths whose DFT size is NL
-// Waves per SIMD the column forward is compiled for: instances that need a
-// few more than 128 VGPRs unbounded (DFT sizes 750 at N = 512, the Bluestein
-// lengths 2N) are held to 128, so that two 512-thread blocks share a CU.
+// Waves per SIMD the column forward is compiled for.  Two instances that
+// need a few more than 128 VGPRs unbounded are held to 128, so that two
+// 512-thread blocks share a CU: DFT size 750 at N = 512 (27.8 -> 18.6 ms per
+// launch, no spills) and the Bluestein length 768 at N = 384 (140 VGPRs ->
+// 128 with 17 spilled; exact-ratio, 3 harmonics x 4 modes: column forward
+// 19.2 -> 15.1 ms per step).  The Bluestein length 512 at N = 256 was slower
+// so bounded (29 spilled; 3.0 -> 3.16 ms) and keeps 156 VGPRs.
 __host__ __device__ constexpr int col_fwd_waves(int N, int nl) {
-  return (N == 512 && nl == 750) ? 4 : 2;
+  return ((N == 512 && nl == 750) || (N == 384 && nl == 768)) ? 4 : 2;
 }
 
 template <int N, int NL>
@@ -1150,7 +1154,15 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   for (int m = 0; m < jb.M; ++m) {
     const gf2* __restrict__ P =
         gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * plane + x0;
-    float2 term[NE];
+    // the mode's probe columns, read once for both positions and issued
+    // before the first transform, which hides their latency (5 harmonics x
+    // 8 modes, N = 512: 175.0 -> 173.7 ms per step)
+    float2 term[NE], pm[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * AT, line = e % G, i = e / G;
+      pm[q] = ldv(P, i * N + line);
+    }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p < np) {
@@ -1166,7 +1178,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * AT, line = e % G, i = e / G;
           const float2 chi = buf[i * LP + line];
-          const float2 pc = cmulconj(ldv(P, i * N + line), chi);  // conj(P) chi
+          const float2 pc = cmulconj(pm[q], chi);  // conj(P) chi
           go[p][q].x = fmaf(sig[p], pc.x, go[p][q].x);
           go[p][q].y = fmaf(sig[p], pc.y, go[p][q].y);
           sgsum[p] += pc.x * o[p][q].x + pc.y * o[p][q].y;
