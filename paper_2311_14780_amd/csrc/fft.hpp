@@ -57,6 +57,16 @@ __device__ __forceinline__ const gf2* opaque_table(P p) {
   return reinterpret_cast<const gf2*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// A wave-uniform global pointer held in scalar registers (loads through it
+// take a scalar base and a vector offset).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+  return reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // Element access that works for generic float2 pointers and for the
 // address-space qualified vector pointers above.
 __device__ __forceinline__ float2 ldv(const float2* p, int i) { return p[i]; }
@@ -498,6 +508,11 @@ __device__ __forceinline__ void fft_first_load(PreIn<n, LINES, NT, LINE_FAST>& i
   }
 }
 
+// Entries of the twiddle table of length n: sum over the passes after the
+// first of Ns (R - 1), i.e. n - R1.
+template <int n>
+constexpr int tw_len() { return n - FirstRadixOf<typename Plan<n>::type>::value; }
+
 // Twiddles loaded per butterfly: w and w^2 (one 16-byte load); the higher
 // powers are products w^r = w^(r/2) w^(r - r/2) (at most a few roundings).
 // Loading all R - 1 values per thread made the twiddle reads the largest
@@ -643,12 +658,18 @@ __device__ __forceinline__ void stockham_run(Buf buf, Tw tw, const PassTw<n, R, 
 template <int n, bool INV, int LINES, int NT, int LP, bool LINE_FAST, class Buf, class Tw,
           class Load, class Store>
 __device__ __forceinline__ void fft_lines(Buf buf, Tw tw, const Load& load, const Store& store) {
-  // The twiddle base is made opaque so that the (loop-invariant) twiddle
-  // loads of an FFT stay inside any loop around the call.
-  const gf2* tg = opaque_table(tw);
   using Plan0 = typename Plan<n>::type;
   PassTw<n, FirstRadixOf<Plan0>::value, LINES, NT> w0;  // the first pass has no twiddles
-  stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, w0, load, store, Plan0{});
+  if constexpr (std::is_same_v<Tw, const lf2*>) {
+    // a table in LDS: its loads wait on the LDS counter, not behind the
+    // global loads in flight
+    stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tw, w0, load, store, Plan0{});
+  } else {
+    // The twiddle base is made opaque so that the (loop-invariant) twiddle
+    // loads of an FFT stay inside any loop around the call.
+    const gf2* tg = opaque_table(tw);
+    stockham_run<n, 1, 0, true, INV, LINES, NT, LP, LINE_FAST>(buf, tg, w0, load, store, Plan0{});
+  }
 }
 
 }  // namespace ptycho
