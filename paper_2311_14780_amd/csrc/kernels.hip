@@ -1003,6 +1003,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
     } else {
       ZIn znext;
       if (m + 1 < jb.M) zload(m + 1, znext);
+      else znext = zcur;  // (no next mode: a defined value, not used)
       fft_lines<NL, true, G, AT, LP, true>(buf, twL, zcur, st_chi);
       zcur = znext;
     }
@@ -1203,6 +1204,8 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
           if (mn < jb.M) {
             const gf2* __restrict__ Zn = z_at(pn, mn);
             fft_first_load(znext, [&](int line, int t) { return zin_at(Zn, line, t); });
+          } else {
+            znext = zcur;  // (no next transform: a defined value, not used)
           }
           fft_lines<NL, true, G, AT, LP, true>(buf, twL, zcur, st_chi);
           zcur = znext;
