@@ -378,7 +378,14 @@ struct Call {
 int job_probe_group(const ptycho_job_t& j, bool want_probe) {
   if (!want_probe) return 1;
   int g = probe_group_of(j.N, j.M, eff_pad(j, 0));
-  for (int l = 1; l < j.L; ++l) g = std::min(g, probe_group_of(j.N, j.M, eff_pad(j, l)));
+  int sets = col_sets_adj(j.N, eff_pad(j, 0));
+  for (int l = 1; l < j.L; ++l) {
+    g = std::min(g, probe_group_of(j.N, j.M, eff_pad(j, l)));
+    sets = std::min(sets, col_sets_adj(j.N, eff_pad(j, l)));
+  }
+  // small scans: one position per block keeps the column adjoint's launch
+  // filled (100 positions at N = 64: 100 -> 400 blocks)
+  if (g > 2 && static_cast<long long>((j.K + g - 1) / g) * sets < kMinGroupedBlocks) g = 1;
   if (g == 2)  // pairs run the paired instance on every wavelength
     for (int l = 0; l < j.L; ++l)
       if (!pair_capable(j.N, eff_pad(j, l))) return 1;
@@ -594,6 +601,7 @@ void fill_job(Call& c, int i, char** cursor) {
   d.n_loss = n_loss_of(j);
   d.want_adjoint = wants_adjoint(c, i) ? 1 : 0;
   d.probe_group = c.pgroup[i];
+  d.obj_tile_h = obj_tile_rows(j.H, j.W, slots_of(j));
   if (c.adam) {
     const ptycho_adam_t& a = c.adam[i];
     float* const m[kVars] = {a.m_object, a.m_probe, a.m_pos, a.m_sigma, a.m_background};
@@ -755,7 +763,9 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
     for (size_t q = 0; q < members.size(); ++q) {
       const ptycho_job_t& j = c.jobs[members[q]];
       if (!cnt[q] || !c.grads[members[q]].g_object) continue;
-      const long long tiles = static_cast<long long>((j.W + 63) / 64) * ((j.H + 15) / 16);
+      const int th = obj_tile_rows(j.H, j.W, slots_of(j));
+      const long long tiles = static_cast<long long>((j.W + kObjTileW - 1) / kObjTileW) *
+                              ((j.H + th - 1) / th);
       for (int l = 0; l < slots_of(j); ++l) ph.add(obj, members[q], l, tiles);
     }
   }

@@ -1386,7 +1386,7 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
 // chunk's windows in parallel and compacts the overlapping ones, in
 // ascending order, into an LDS list (wave ballots), then accumulates over
 // that list only.  units: (l, tile)
-constexpr int kTileW = 64, kTileH = 16;
+constexpr int kTileW = kObjTileW, kTileHMax = 16;
 constexpr int kListMax = 1024;  // windows tested per round
 __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   const UnitRef r = decode<1>(la);
@@ -1396,18 +1396,21 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
   __shared__ int wave_cnt[NT / 64];
   const int N = jb.N, l = r.l;
   const int tiles_x = (jb.W + kTileW - 1) / kTileW;
+  const int TH = jb.obj_tile_h;  // 4, 8 or 16 rows
   const int ty = r.u / tiles_x, txi = r.u - ty * tiles_x;
-  const int tx0 = txi * kTileW, ty0 = ty * kTileH;
+  const int tx0 = txi * kTileW, ty0 = ty * TH;
   const int tx = threadIdx.x % kTileW, tyb = threadIdx.x / kTileW;  // tyb in [0, 4)
   const int x = tx0 + tx;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  constexpr int PER = kTileH / (NT / kTileW);
+  constexpr int PER = kTileHMax / (NT / kTileW);  // rows per thread, at most
+  const int per = TH / (NT / kTileW);
   float2 acc[PER];
   gf2* __restrict__ G = gmem(jb.g_object) + static_cast<size_t>(l) * jb.H * jb.W;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int y = ty0 + tyb + q * (NT / kTileW);
-    acc[q] = (x < jb.W && y < jb.H) ? ldv(G, static_cast<size_t>(y) * jb.W + x) : make_float2(0.f, 0.f);
+    acc[q] = (q < per && x < jb.W && y < jb.H) ? ldv(G, static_cast<size_t>(y) * jb.W + x)
+                                              : make_float2(0.f, 0.f);
   }
   const size_t plane = static_cast<size_t>(N) * N;
   const int C = min(jb.C, jb.K - la.iter * jb.C);
@@ -1423,7 +1426,7 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
       if (s0 + threadIdx.x < cn) {
         float dy, dx;
         split_pos(pos, kbase + c, py, px, dy, dx);
-        hit = !(py >= ty0 + kTileH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0);
+        hit = !(py >= ty0 + TH || py + N <= ty0 || px >= tx0 + kTileW || px + N <= tx0);
       }
       const unsigned long long m = __ballot(hit);
       if (lane == 0) wave_cnt[wid] = __popcll(m);
@@ -1461,7 +1464,7 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
           const int yr = ty0 + tyb + q * (NT / kTileW) - py;
-          ok[h][q] = inx && yr >= 0 && yr < N;
+          ok[h][q] = q < per && inx && yr >= 0 && yr < N;
           v[h][q] = ok[h][q] ? ldv(GA, yr * N + xr) : make_float2(0.f, 0.f);
         }
       }
@@ -1476,7 +1479,7 @@ __global__ __launch_bounds__(NT) void k_obj_gather(Launch la) {
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int y = ty0 + tyb + q * (NT / kTileW);
-    if (x < jb.W && y < jb.H) stv(G, static_cast<size_t>(y) * jb.W + x, acc[q]);
+    if (q < per && x < jb.W && y < jb.H) stv(G, static_cast<size_t>(y) * jb.W + x, acc[q]);
   }
 }
 
@@ -1741,6 +1744,15 @@ int probe_group_of(int N, int M, int nl) {
   if (acc + buf <= kColAdjLds) return kProbeGroup;
   if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + buf <= kColAdjLds) return 2;
   return 1;
+}
+
+int col_sets_adj(int N, int nl) { return N / col_group_adj(N, nl); }
+
+int obj_tile_rows(int H, int W, int slots) {
+  const long long tiles16 =
+      static_cast<long long>((W + kObjTileW - 1) / kObjTileW) * ((H + 15) / 16) * slots;
+  if (tiles16 >= 1024) return 16;
+  return tiles16 * 2 >= 1024 ? 8 : 4;
 }
 
 size_t col_adj_pair_lds(int N, int nl) {

@@ -74,6 +74,7 @@ struct JobDev {
   int want_adjoint;
   int probe_group;      // positions whose probe-gradient terms one column-adjoint
                         // block sums in LDS (1: one term per position)
+  int obj_tile_h;       // rows of the object-gradient gather's tiles (4, 8 or 16)
   // Flat float views selected by a segment's l in the gradient-zeroing and
   // Adam launches (0 object, 1 probe, 2 positions, 3 sigma, 4 background).
   // The host fills them so that those kernels pick their arrays by index:
@@ -153,6 +154,16 @@ int adj_part_stride(int N);
 // over its slots' sizes, and 1 for a job with an exact-ratio wavelength whose
 // least is 2 (the paired instance is zero-padded only).
 int probe_group_of(int N, int M, int nl);
+// Groups of four only pay when the launch keeps enough blocks to fill the
+// GPU (two per CU): a job with fewer than this many (positions / 4 x column
+// sets) takes groups of one.
+constexpr long long kMinGroupedBlocks = 512;
+// Column sets (blocks per position) of the column-adjoint instance of DFT size nl.
+int col_sets_adj(int N, int nl);
+// Rows of the object-gather tiles of a job: 16, or 8 or 4 when 16-row tiles
+// would give fewer than 1024 blocks (small objects: more, shorter blocks).
+int obj_tile_rows(int H, int W, int slots);
+constexpr int kObjTileW = 64;
 // The paired column-adjoint instance exists for (N, nl).
 bool pair_capable(int N, int nl);
 // Dynamic LDS bytes of the paired column-adjoint instance.

@@ -73,12 +73,18 @@ def test_workspace_bytes_scale_with_chunk():
     # per position: X, GX (L N^2 c64 each), Y (L M N^2 c64), ramps, partials
     per = 8 * 64 * 64 * (2 * 2 + 2 * 3)
     assert b_all - b_one >= 3 * per
-    # loss + gradient calls take positions in groups of 4 for the probe
-    # gradient: a smaller chunk is rounded up to the group
-    assert _ws_bytes(j, chunk=1) == _ws_bytes(j, chunk=4)
-    assert _ws_bytes(j, chunk=5) == _ws_bytes(j, chunk=8)
+    # a scan this small takes one position per column-adjoint block (groups of
+    # four would leave the launch with 20 blocks): chunks are not rounded
+    assert _ws_bytes(j, chunk=1)[1] < _ws_bytes(j, chunk=2)[1]
+    # with enough positions (1100 / 4 x 4 column sets >= 512 blocks) loss +
+    # gradient calls take positions in groups of 4 for the probe gradient:
+    # a smaller chunk is rounded up to the group
+    big = _job(K=1100)
+    assert _ws_bytes(big, chunk=1) == _ws_bytes(big, chunk=4)
+    assert _ws_bytes(big, chunk=5) == _ws_bytes(big, chunk=8)
+    assert _ws_bytes(big, chunk=4)[1] < _ws_bytes(big, chunk=5)[1]
     # the forward pass does not group positions
-    assert _ws_bytes(j, which=0, chunk=1)[1] < _ws_bytes(j, which=0, chunk=2)[1]
+    assert _ws_bytes(big, which=0, chunk=1)[1] < _ws_bytes(big, which=0, chunk=2)[1]
 
 
 @pytest.mark.parametrize("change,code", [

@@ -14,9 +14,10 @@ DEV = "cuda:0"
 ALL = ("object", "probe", "pos", "sigma", "background", "ratio")
 
 
-def _c1(K=7, Ns=1, exact=True, **kw):
+def _c1(K=7, Ns=1, exact=True, scan=None, **kw):
     w = synth.reduced(synth.get_workload("C1"), L=2, M=2, Ns=Ns, harmonics=(19, 23),
-                      mode_weights=(0.75, 0.25), K=K, name=f"C1-edge{K}")
+                      mode_weights=(0.75, 0.25), K=K, name=f"C1-edge{K}",
+                      **({"scan": scan} if scan else {}))
     pads = synth.ratios_for(w.N, w.harmonics, w.ref_harmonic) if exact else (80, 64)
     return U.make_case(w, pads=pads, **kw)
 
@@ -46,10 +47,14 @@ def test_exact_ratio_window_outside_reports_erange():
         assert not np.any(got[k]), k
 
 
-@pytest.mark.parametrize("K,chunk", [(5, 2), (9, 3), (13, 0)])
+@pytest.mark.parametrize("K,chunk", [(5, 2), (9, 3), (13, 0), (517, 130)])
 def test_ragged_position_counts_and_chunks(K, chunk):
-    # groups of 4 positions, chunks rounded to the group, a ragged last chunk
-    case = _c1(K=K, with_sigma=True, with_bg=True)
+    # Ragged position counts and chunks.  Scans this small take one position
+    # per column-adjoint block; 517 positions (a spiral over the object) take
+    # groups of 4 (130 groups x 4 column sets >= 512 blocks): chunks rounded
+    # up to the group (132), a ragged last chunk (121) and last group (1).
+    kw = dict(scan="spiral") if K > 100 else {}
+    case = _c1(K=K, with_sigma=True, with_bg=True, **kw)
     prob = U.to_problem(case, DEV)
     got = U.gpu_grads(prob, want=ALL, chunk=chunk)
     print(K, chunk, U.compare(got, U.oracle_grads(case)))
