@@ -190,9 +190,11 @@ int32_t ptycho_supported(int32_t N, int32_t pad);
    for these jobs with at most `chunk` positions per pass (chunk <= 0: all K).
    Any workspace of at least the chunk = 1 size works; a larger workspace
    lets the library process more positions per launch.  Loss + gradient
-   calls process the positions of a job in groups of up to 4 (the probe
-   gradient of a group is summed in on-chip memory), so for them `chunk` is
-   rounded up to a multiple of the job's group size.  Only the size fields
+   calls that want the probe gradient sum it over groups of consecutive
+   positions of a job (4 when the sums fit in on-chip memory and the scan
+   is long enough to keep the launch filled, 2 when they do not fit, else 1;
+   a function of the job alone), so for them `chunk` is rounded up to a
+   multiple of the job's group size.  Only the size fields
    (K, L, M, N, H, W, pad, ratio) and whether rs_idx is non-NULL are read: the array
    pointers may be NULL, so a scheduler can size a call before allocating. */
 int32_t ptycho_workspace_bytes(const ptycho_job_t* jobs, int32_t n_jobs, int32_t which,
