@@ -98,6 +98,16 @@ __host__ __device__ constexpr bool adj_narrow(int N, int nl) {
 __host__ __device__ constexpr int col_group_adj(int N, int nl) {
   return adj_narrow(N, nl) ? 8 : (N <= 256 ? 16 : 8);
 }
+// Row pitch (in elements) of the column adjoints' LDS transform buffer,
+// whose rows hold the G columns of one element index.  Unpadded rows for
+// the zero-padded sizes at N >= 384 (5 harmonics x 8 modes at N = 512:
+// column adjoint 172.3 -> 162.8 ms per step; 3 x 4 at N = 384: 14.4 -> 14.1
+// ms); one element of padding at N <= 256, where the unpadded rows were
+// slower (4 x 3 at N = 256: +0.03 ms), and for the Bluestein lengths 2N,
+// whose instances then spill.  Pitches G + 2 and G + 3 were no faster.
+__host__ __device__ constexpr int col_adj_lp(int N, int nl, int G) {
+  return (N >= 384 && nl != 2 * N) ? G : G + 1;
+}
 // Threads per block of the column adjoint instance.
 __host__ __device__ constexpr int col_adj_threads(int N, int nl) { return CNT; }
 // Row stride of the column adjoint's per-block partial sums ([C][L][stride]):
@@ -357,14 +367,20 @@ __global__ __launch_bounds__(NT) void k_czt_tables(Launch la) {
 template <int N>
 __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   constexpr int RB = rb_row<N>();
+  // each wave transforms RW of the block's RB rows in an LDS region of its
+  // own, so the passes need no workgroup barriers
+  constexpr int RW = RB / (NT / 64);
+  static_assert(RB % (NT / 64) == 0, "whole rows per wave");
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   constexpr int LP = row_lp(N);
   using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[RB * LP];
+  const int wv = static_cast<int>(threadIdx.x >> 6);
+  lf2* const bufw = (lf2*)buf + wv * RW * LP;
   const int l = r.l, c = r.u, k = la.iter * jb.C + c;
-  const int y0 = r.sub * RB;
+  const int y0 = r.sub * RB + wv * RW;
   int py, px;
   float dy, dx;
   split_pos(gmem(jb.pos), k, py, px, dy, dx);
@@ -374,15 +390,15 @@ __global__ __launch_bounds__(NT) void k_row_fwd(Launch la) {
   const float2* __restrict__ tw = jb.tw_N;
   const int Wd = jb.W;
   auto ld_obj = [&](int line, int i) { return ldv(O, line * Wd + i); };
-  auto st_ramp = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = cmul(v, ldv(rx, i)); };
-  fft_lines<N, false, RB, NT, LP, false>(buf, tw, ld_obj, st_ramp);
+  auto st_ramp = [&](int line, int i, float2 v) { stv(bufw, Ix::at(line, i), cmul(v, ldv(rx, i))); };
+  fft_lines<N, false, RW, 64, LP, false>(bufw, tw, ld_obj, st_ramp);
   gf2* __restrict__ X = gmem(jb.X) + ((static_cast<size_t>(c) * jb.L + l) * N + y0) * N;
   constexpr float inv = 1.0f / N;
-  auto ld_buf = [&](int line, int i) { return buf[Ix::at(line, i)]; };
+  auto ld_buf = [&](int line, int i) { return ldv(bufw, Ix::at(line, i)); };
   // streaming stores of whole rows (row forward, 400 positions x 4 wavelengths
   // at N = 256: 0.266 -> 0.225 ms; 900 x 3 at N = 384: 1.02 -> 0.87 ms)
   auto st_x = [&](int line, int i, float2 v) { stv_nt(X, line * N + i, cscale(v, inv)); };
-  fft_lines<N, true, RB, NT, LP, false>(buf, tw, ld_buf, st_x);
+  fft_lines<N, true, RW, 64, LP, false>(bufw, tw, ld_buf, st_x);
 }
 
 // ---------------------------------------------------------- column forward
@@ -881,7 +897,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   const bool want_probe = jb.g_probe != nullptr;
-  constexpr int LP = G + 1;
+  constexpr int LP = col_adj_lp(N, NL, G);
   constexpr int NE = N * G / AT;
   __shared__ float2 buf[NL * LP];
   __shared__ float red[AT / 64];
@@ -1097,7 +1113,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
   constexpr int G = col_group_adj(N, NL);
   constexpr int AT = col_adj_threads(N, NL);
-  constexpr int LP = G + 1;
+  constexpr int LP = col_adj_lp(N, NL, G);
   constexpr int NE = N * G / AT;
   const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
@@ -1336,12 +1352,16 @@ __global__ __launch_bounds__(NT) void k_bg_reduce(Launch la) {
 }
 
 // -------------------------------------------------------------- row adjoint
-// lines [0, RB): G_X rows; [RB, 2 RB): X rows.  x-position derivative from
+// per wave, lines [0, RW): G_X rows; [RW, 2 RW): X rows.  x-position derivative from
 // Re sum conj(FFT(G_X)) (2 pi i nu) FFT(X) / N; G_A = IFFT(conj(ramp) FFT(G_X)) / N
 // units: (l, c)
 template <int N>
 __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   constexpr int RB = rb_adj<N>();
+  // each wave owns RW of the block's RB rows (their G_X and X lines) in an
+  // LDS region of its own; the waves meet only in the block sum
+  constexpr int RW = RB / (NT / 64);
+  static_assert(RB % (NT / 64) == 0, "whole rows per wave");
   const UnitRef r = decode<N / RB>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
@@ -1349,7 +1369,9 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   using Ix = Lds<N, LP, false>;
   __shared__ float2 buf[2 * RB * LP];
   __shared__ float red[NT / 64];
-  const int l = r.l, c = r.u, y0 = r.sub * RB;
+  const int wv = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+  lf2* const bufw = (lf2*)buf + wv * 2 * RW * LP;
+  const int l = r.l, c = r.u, y0 = r.sub * RB + wv * RW;
   const int tid = threadIdx.x;
   const size_t off = (static_cast<size_t>(c) * jb.L + l) * N * N + static_cast<size_t>(y0) * N;
   const gf2* __restrict__ GXr = gmem(jb.GX) + off;
@@ -1357,24 +1379,24 @@ __global__ __launch_bounds__(NT) void k_row_adj(Launch la) {
   const gf2* __restrict__ rx = gmem(jb.ramp) + (static_cast<size_t>(c) * 2 + 1) * N;
   const float2* __restrict__ twN = jb.tw_N;
   auto ld = [&](int line, int i) {
-    return line < RB ? ldv(GXr, line * N + i) : ldv(Xr, (line - RB) * N + i);
+    return line < RW ? ldv(GXr, line * N + i) : ldv(Xr, (line - RW) * N + i);
   };
-  auto st = [&](int line, int i, float2 v) { buf[Ix::at(line, i)] = v; };
-  fft_lines<N, false, 2 * RB, NT, LP, false>(buf, twN, ld, st);
+  auto st = [&](int line, int i, float2 v) { stv(bufw, Ix::at(line, i), v); };
+  fft_lines<N, false, 2 * RW, 64, LP, false>(bufw, twN, ld, st);
   float dsum = 0.f;
-  for (int e = tid; e < RB * N; e += NT) {
+  for (int e = lane; e < RW * N; e += 64) {
     const int line = e / N, i = e % N;
-    const float2 gh = buf[Ix::at(line, i)];
-    const float2 xh = buf[Ix::at(line + RB, i)];
+    const float2 gh = ldv(bufw, Ix::at(line, i));
+    const float2 xh = ldv(bufw, Ix::at(line + RW, i));
     const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
     dsum += nu * (gh.y * xh.x - gh.x * xh.y);
-    buf[Ix::at(line, i)] = cmul(gh, cconj(ldv(rx, i)));
+    stv(bufw, Ix::at(line, i), cmul(gh, cconj(ldv(rx, i))));
   }
-  __syncthreads();
+  fft_sync<64>();  // the inverse reads other lanes' elements
   constexpr float invN = 1.0f / N;
-  auto ld1 = [&](int line, int i) { return buf[Ix::at(line, i)]; };
+  auto ld1 = [&](int line, int i) { return ldv(bufw, Ix::at(line, i)); };
   auto st1 = [&](int line, int i, float2 v) { stv(Xr, line * N + i, cscale(v, invN)); };
-  fft_lines<N, true, RB, NT, LP, false>(buf, twN, ld1, st1);
+  fft_lines<N, true, RW, 64, LP, false>(bufw, twN, ld1, st1);
   const float s = block_sum(dsum, red);
   if (tid == 0) gmem(jb.dx_part)[(static_cast<size_t>(c) * jb.L + l) * (N / RB) + r.sub] = s * invN;
 }
@@ -1740,7 +1762,7 @@ bool pair_capable(int N, int nl) { return N >= 256 && nl != czt_len(N); }
 int probe_group_of(int N, int M, int nl) {
   const size_t G = static_cast<size_t>(col_group_adj(N, nl));
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
-  const size_t buf = static_cast<size_t>(nl) * (G + 1) * sizeof(float2);
+  const size_t buf = static_cast<size_t>(nl) * col_adj_lp(N, nl, static_cast<int>(G)) * sizeof(float2);
   if (acc + buf <= kColAdjLds) return kProbeGroup;
   if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + buf <= kColAdjLds) return 2;
   return 1;
