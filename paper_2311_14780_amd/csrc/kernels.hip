@@ -98,16 +98,22 @@ __host__ __device__ constexpr bool adj_narrow(int N, int nl) {
 __host__ __device__ constexpr int col_group_adj(int N, int nl) {
   return adj_narrow(N, nl) ? 8 : (N <= 256 ? 16 : 8);
 }
-// Row pitch (in elements) of the column adjoints' LDS transform buffer,
-// whose rows hold the G columns of one element index.  Unpadded rows for
-// the zero-padded sizes at N >= 384 (5 harmonics x 8 modes at N = 512:
-// column adjoint 172.3 -> 162.8 ms per step; 3 x 4 at N = 384: 14.4 -> 14.1
-// ms); one element of padding at N <= 256, where the unpadded rows were
-// slower (4 x 3 at N = 256: +0.03 ms), and for the Bluestein lengths 2N,
-// whose instances then spill.  Pitches G + 2 and G + 3 were no faster.
+// Row pitch (in elements) of the block-wide column adjoint's LDS transform
+// buffer, whose rows hold the G columns of one element index.  Unpadded
+// rows for the zero-padded sizes at N >= 384 (3 harmonics x 4 modes at
+// N = 384: 14.4 -> 14.1 ms per step; the paired kernel, while its transforms
+// were block-wide too, went 172.3 -> 162.8 ms at 5 x 8, N = 512); one
+// element of padding at N <= 256, where the unpadded rows were slower
+// (4 x 3 at N = 256: +0.03 ms), and for the Bluestein lengths 2N, whose
+// instances then spill.  Pitches G + 2 and G + 3 were no faster.
 __host__ __device__ constexpr int col_adj_lp(int N, int nl, int G) {
   return (N >= 384 && nl != 2 * N) ? G : G + 1;
 }
+// Row pitch of the paired column adjoint, whose waves each transform their
+// own columns of the buffer: an odd pitch spreads a column's elements over
+// the LDS banks (unpadded rows, 8 columns at N = 512: 254 ms per step of 5
+// harmonics x 8 modes against 158 ms with one element of padding).
+__host__ __device__ constexpr int col_pair_lp(int G) { return G + 1; }
 // Threads per block of the column adjoint instance.
 __host__ __device__ constexpr int col_adj_threads(int N, int nl) { return CNT; }
 // Row stride of the column adjoint's per-block partial sums ([C][L][stride]):
@@ -1113,7 +1119,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
   constexpr int G = col_group_adj(N, NL);
   constexpr int AT = col_adj_threads(N, NL);
-  constexpr int LP = col_adj_lp(N, NL, G);
+  constexpr int LP = col_pair_lp(G);
   constexpr int NE = N * G / AT;
   const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
@@ -1179,30 +1185,40 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   }
 
   // chi_{p,m} = crop(DFT^H(embed(Z_{p,m}))); go_p += sig_p conj(P_m) chi;
-  // probe term sum_p sig_p conj(Osh_p) chi
-  auto st_chi = [&](int line, int t, float2 v) {
-    if (t < N) buf[t * LP + line] = cscale(v, ps);
-  };
+  // probe term sum_p sig_p conj(Osh_p) chi.  The block stores the Z tile of
+  // a transform (rows u < N of its G columns, coalesced) in the buffer,
+  // then each wave transforms its columns there on its own (wave fences, no
+  // workgroup barrier per pass), and the block meets again for the
+  // pointwise products.  The next tile's loads are in flight meanwhile.
+  constexpr int LW = G / (AT / 64);  // columns per wave
+  static_assert(G % (AT / 64) == 0, "whole columns per wave");
   auto z_at = [&](int p, int m) {
     return gmem(jb.Y) + ((static_cast<size_t>(c0 + p) * jb.L + l) * jb.M + m) * plane + x0;
   };
-  auto zin_at = [&](const gf2* __restrict__ Zm, int line, int t) {
+  float2 zt[NE];  // element e = tid + q AT of the tile: column e % G, row e / G
+  auto zload = [&](int p, int m) {
+    const gf2* __restrict__ Zm = z_at(p, m);
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * AT, line = e % G, i = e / G;
+      zt[q] = ldv(Zm, i * N + line);
+    }
+  };
+  // this wave's columns: element t of column j at colw[t LP + j]
+  lf2* const colw = (lf2*)buf + (tid >> 6) * LW;
+  auto ld_w = [&](int j, int t) {
     int u = t + N / 2;
     if (u >= NL) u -= NL;
-    return u < N ? ldv(Zm, u * N + line) : make_float2(0.f, 0.f);
+    return u < N ? ldv(colw, u * LP + j) : make_float2(0.f, 0.f);
   };
-  using ZIn = PreIn<NL, G, AT, true>;
-  ZIn zcur;
-  {
-    const gf2* __restrict__ Zf = z_at(0, 0);
-    fft_first_load(zcur, [&](int line, int t) { return zin_at(Zf, line, t); });
-  }
+  auto st_w = [&](int j, int t, float2 v) {
+    if (t < N) stv(colw, t * LP + j, cscale(v, ps));
+  };
+  zload(0, 0);
   for (int m = 0; m < jb.M; ++m) {
     const gf2* __restrict__ P =
         gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * plane + x0;
-    // the mode's probe columns, read once for both positions and issued
-    // before the first transform, which hides their latency (5 harmonics x
-    // 8 modes, N = 512: 175.0 -> 173.7 ms per step)
+    // the mode's probe columns, read once for both positions
     float2 term[NE], pm[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
@@ -1212,20 +1228,20 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p < np) {
-        {
-          // the next transform's inputs (position 1 of this mode, else
-          // position 0 of the next mode) are in flight during this one
-          const int pn = (p == 0 && np == 2) ? 1 : 0, mn = pn ? m : m + 1;
-          ZIn znext;
-          if (mn < jb.M) {
-            const gf2* __restrict__ Zn = z_at(pn, mn);
-            fft_first_load(znext, [&](int line, int t) { return zin_at(Zn, line, t); });
-          } else {
-            znext = zcur;  // (no next transform: a defined value, not used)
-          }
-          fft_lines<NL, true, G, AT, LP, true>(buf, twL, zcur, st_chi);
-          zcur = znext;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const int e = tid + q * AT, line = e % G, i = e / G;
+          buf[i * LP + line] = zt[q];
         }
+        {
+          // the next transform's tile: position 1 of this mode, else
+          // position 0 of the next mode
+          const int pn = (p == 0 && np == 2) ? 1 : 0, mn = pn ? m : m + 1;
+          if (mn < jb.M) zload(pn, mn);
+        }
+        __syncthreads();
+        fft_lines<NL, true, LW, 64, LP, true>(colw, twL, ld_w, st_w);
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * AT, line = e % G, i = e / G;
@@ -1764,7 +1780,8 @@ int probe_group_of(int N, int M, int nl) {
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
   const size_t buf = static_cast<size_t>(nl) * col_adj_lp(N, nl, static_cast<int>(G)) * sizeof(float2);
   if (acc + buf <= kColAdjLds) return kProbeGroup;
-  if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + buf <= kColAdjLds) return 2;
+  const size_t pbuf = static_cast<size_t>(nl) * col_pair_lp(static_cast<int>(G)) * sizeof(float2);
+  if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + pbuf <= kColAdjLds) return 2;
   return 1;
 }
 
