@@ -192,7 +192,7 @@ int32_t ptycho_supported(int32_t N, int32_t pad);
    lets the library process more positions per launch.  Loss + gradient
    calls that want the probe gradient sum it over groups of consecutive
    positions of a job (4 when the sums fit in on-chip memory and the scan
-   is long enough to keep the launch filled, 2 when they do not fit, else 1;
+   is long enough to keep the launch filled, 3 when they do not fit, else 1;
    a function of the job alone), so for them `chunk` is rounded up to a
    multiple of the job's group size.  Only the size fields
    (K, L, M, N, H, W, pad, ratio) and whether rs_idx is non-NULL are read: the array

@@ -304,7 +304,7 @@ size_t per_position_bytes(const ptycho_job_t& j, int which) {
 // most one segment per (job, selector) and launch, so the bound follows from
 // the selectors each phase enumerates:
 //  - a chunk iteration: 5 per slot (row forward, column forward, column
-//    adjoint (the plain or the paired launch, never both for one job), row
+//    adjoint (the plain or the grouped-position launch, never both), row
 //    adjoint, object gather), one per wavelength (probe
 //    reduction) and one each for ramps, detector, background sum, finalise;
 //  - the prologue: one per gradient output (kVars + distance ratio), status,
@@ -385,10 +385,12 @@ int job_probe_group(const ptycho_job_t& j, bool want_probe) {
   }
   // small scans: one position per block keeps the column adjoint's launch
   // filled (100 positions at N = 64: 100 -> 400 blocks)
-  if (g > 2 && static_cast<long long>((j.K + g - 1) / g) * sets < kMinGroupedBlocks) g = 1;
-  if (g == 2)  // pairs run the paired instance on every wavelength
+  if (g >= 4 && static_cast<long long>((j.K + g - 1) / g) * sets < kMinGroupedBlocks) g = 1;
+  // register groups run the grouped-position instance on every wavelength:
+  // each must have it and fit it
+  if (g == kRegGroup)
     for (int l = 0; l < j.L; ++l)
-      if (!pair_capable(j.N, eff_pad(j, l))) return 1;
+      if (!pair_fits(j.N, eff_pad(j, l), kRegGroup)) return 1;
   return g;
 }
 
@@ -733,14 +735,15 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
   for (size_t q = 0; q < members.size(); ++q) ph.add(det, members[q], 0, cnt[q]);
   Phase::Item prob = ph.begin(), rowa = ph.begin(), obj = ph.begin();
   if (key.adjoint) {
-    // jobs with probe-gradient pairs run the paired instance (its own launch)
+    // jobs with register groups run the grouped-position instance (its own
+    // launch)
     for (size_t p = 0; p < nls.size(); ++p) {
       for (int pass = 0; pass < 2; ++pass) {
         Phase::Item& it = pass == 0 ? cola[p] : colp[p];
         it = ph.begin();
         for (size_t q = 0; q < members.size(); ++q) {
           const int pg = c.pgroup[members[q]];
-          if ((pg == 2) != (pass == 1)) continue;
+          if ((pg == kRegGroup) != (pass == 1)) continue;
           for (int l = 0; l < slots_of(c.jobs[members[q]]); ++l)
             if (eff_pad_slot(c.jobs[members[q]], l) == nls[p])
               ph.add(it, members[q], l, (cnt[q] + pg - 1) / pg);
@@ -815,7 +818,7 @@ int run_iteration(Call& c, const GroupKey& key, const std::vector<int>& members,
         bool uses = false;
         for (int l = 0; l < j.L; ++l) uses |= eff_pad(j, l) == nls[p];
         if (!uses || !cnt[q]) continue;
-        if (c.pgroup[members[q]] == 2) continue;  // paired launch below
+        if (c.pgroup[members[q]] == kRegGroup) continue;  // grouped-position launch below
         grouped |= c.pgroup[members[q]] > 1;
         lds = std::max(lds, col_adj_lds_of(N, nls[p], j.M, c.pgroup[members[q]]));
       }

@@ -1101,19 +1101,22 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   }
 }
 
-// Column adjoint over pairs of consecutive positions: the probe-gradient
-// groups of two of jobs whose [M][N][G] LDS accumulator does not fit (many
-// modes at N = 512).  The modes are the outer loop: for mode m the block
-// transforms both positions' columns and adds their probe-gradient terms in
-// registers, in ascending position order, and writes the sum once, into the
-// first position's slot.  So the probe columns of a mode are read once per
-// pair, and the terms that the column adjoint writes and the probe reduction
-// reads halve.  Per position the arithmetic is that of k_col_adj (the same
-// transforms and products), and the pair's sum t0 + t1 is the value that a
-// two-position LDS group forms.  Ohat of both positions waits in LDS
-// (dynamic, [2][N][G]) until the y-shift adjoint at the end; the shifted
-// patches and the gradients go_p stay in registers.
-// units: (l, pair of positions) for the wavelengths whose DFT size is NL.
+// Column adjoint over groups of PG = kRegGroup (3) consecutive positions: the
+// probe-gradient groups of jobs whose [M][N][G] LDS accumulator does not fit
+// (many modes at N = 512).  The modes are the outer loop: for mode m the
+// block transforms the group's columns and adds their probe-gradient terms
+// in registers, in ascending position order, and writes the sum once, into
+// the first position's slot.  So the probe columns of a mode are read once
+// per group, and the terms that the column adjoint writes and the probe
+// reduction reads are divided by PG.  Per position the arithmetic is that of
+// k_col_adj (the same transforms and products), and the group's sum
+// ((t0 + t1) + t2) is the value that an LDS group of the same positions
+// forms.  Ohat of the group's positions waits in LDS (dynamic, [PG][N][G])
+// until the y-shift adjoint at the end; the shifted patches and the
+// gradients go_p stay in registers.  Three positions rather than two (5
+// harmonics x 8 modes, N = 512: column adjoint 159.4 -> 151.5 ms, probe
+// reduction 17.1 -> 11.4 ms per step); every compiled size fits them.
+// units: (l, group of PG positions) for the wavelengths whose DFT size is NL.
 template <int N, int NL>
 __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Launch la) {
   static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
@@ -1126,7 +1129,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   if (*gmem(jb.status)) return;
   __shared__ float2 buf[NL * LP];
   __shared__ float red[AT / 64];
-  extern __shared__ float2 ohs[];  // [2][N * G], element e of this thread at e = tid + q AT
+  extern __shared__ float2 ohs[];  // [PG][N * G], element e of this thread at e = tid + q AT
   // The twiddle tables are copied to LDS and the transforms read them there:
   // the next transform's column inputs are loaded during the current one,
   // and a twiddle load from global memory issued after them would make the
@@ -1137,8 +1140,9 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   __shared__ float2 tws[TWL + TWN];
   const int l = r.l, x0 = r.sub * G;
   const int tid = threadIdx.x;
-  const int c0 = r.u * 2;
-  const int np = min(2, min(jb.C, jb.K - la.iter * jb.C) - c0);  // 1 or 2
+  constexpr int PG = kRegGroup;
+  const int c0 = r.u * PG;
+  const int np = min(PG, min(jb.C, jb.K - la.iter * jb.C) - c0);  // 1 .. PG
   const bool want_probe = jb.g_probe != nullptr;
   {
     const gf2* __restrict__ gL = gmem(jb.tw_pad[l]);
@@ -1154,12 +1158,12 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   constexpr float invN = 1.0f / N;
   auto ld_buf = [&](int line, int i) { return buf[i * LP + line]; };
   auto st_buf = [&](int line, int i, float2 v) { buf[i * LP + line] = v; };
-  float2 o[2][NE], go[2][NE];
-  float sig[2], sgsum[2] = {0.f, 0.f};
+  float2 o[PG][NE], go[PG][NE];
+  float sig[PG], sgsum[PG] = {};
 
   // recompute Ohat = ramp_y FFT_y(X) (to LDS) and Osh = IFFT_y(Ohat) / N
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < PG; ++p) {
     if (p < np) {
       const int c = c0 + p, k = la.iter * jb.C + c;
       const gf2* __restrict__ X = gmem(jb.X) + (static_cast<size_t>(c) * jb.L + l) * plane + x0;
@@ -1218,7 +1222,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   for (int m = 0; m < jb.M; ++m) {
     const gf2* __restrict__ P =
         gmem(jb.probe) + (static_cast<size_t>(l / jb.Ns) * jb.M + m) * plane + x0;
-    // the mode's probe columns, read once for both positions
+    // the mode's probe columns, read once for the group's positions
     float2 term[NE], pm[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
@@ -1226,7 +1230,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
       pm[q] = ldv(P, i * N + line);
     }
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < PG; ++p) {
       if (p < np) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
@@ -1234,9 +1238,9 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
           buf[i * LP + line] = zt[q];
         }
         {
-          // the next transform's tile: position 1 of this mode, else
-          // position 0 of the next mode
-          const int pn = (p == 0 && np == 2) ? 1 : 0, mn = pn ? m : m + 1;
+          // the next transform's tile: the next position of this mode,
+          // else position 0 of the next mode
+          const int pn = p + 1 < np ? p + 1 : 0, mn = pn ? m : m + 1;
           if (mn < jb.M) zload(pn, mn);
         }
         __syncthreads();
@@ -1272,7 +1276,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   // per position: sigma partial, Ghat = FFT_y(go) (y-position derivative),
   // adjoint y-shift to GX
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < PG; ++p) {
     if (p < np) {
       const int c = c0 + p;
       const size_t slot = (static_cast<size_t>(c) * jb.L + l) * adj_stride(N) + r.sub;
@@ -1771,6 +1775,7 @@ constexpr int kProbeGroup = 4;
 // LDS a column-adjoint block may use (gfx950: 160 KB per workgroup), less a
 // margin for the reduction scratch.
 constexpr size_t kColAdjLds = 156 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;  // LDS of one workgroup
 
 // Zero-padded DFT sizes of N >= 256 have a paired column-adjoint instance.
 bool pair_capable(int N, int nl) { return N >= 256 && nl != czt_len(N); }
@@ -1780,8 +1785,7 @@ int probe_group_of(int N, int M, int nl) {
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
   const size_t buf = static_cast<size_t>(nl) * col_adj_lp(N, nl, static_cast<int>(G)) * sizeof(float2);
   if (acc + buf <= kColAdjLds) return kProbeGroup;
-  const size_t pbuf = static_cast<size_t>(nl) * col_pair_lp(static_cast<int>(G)) * sizeof(float2);
-  if (pair_capable(N, nl) && col_adj_pair_lds(N, nl) + pbuf <= kColAdjLds) return 2;
+  if (pair_fits(N, nl, kRegGroup)) return kRegGroup;
   return 1;
 }
 
@@ -1794,8 +1798,18 @@ int obj_tile_rows(int H, int W, int slots) {
   return tiles16 * 2 >= 1024 ? 8 : 4;
 }
 
-size_t col_adj_pair_lds(int N, int nl) {
-  return 2 * static_cast<size_t>(N) * col_group_adj(N, nl) * sizeof(float2);
+size_t col_adj_pair_lds(int N, int nl, int pg) {
+  return static_cast<size_t>(pg) * N * col_group_adj(N, nl) * sizeof(float2);
+}
+
+// Whether the grouped column adjoint over pg positions fits in a block's
+// LDS: Ohat of the group (dynamic) next to the transform buffer, the twiddle
+// tables (at most nl + N entries) and the block sums.
+bool pair_fits(int N, int nl, int pg) {
+  if (!pair_capable(N, nl)) return false;
+  const size_t G = static_cast<size_t>(col_group_adj(N, nl));
+  const size_t stat = (static_cast<size_t>(nl) * col_pair_lp(static_cast<int>(G)) + nl + N) * sizeof(float2) + 64;
+  return col_adj_pair_lds(N, nl, pg) + stat <= kLdsMax;
 }
 
 size_t col_adj_lds_of(int N, int nl, int M, int group) {
@@ -1925,7 +1939,7 @@ hipError_t launch_col_adj_inst(dim3 g, const Launch& la, size_t dyn_lds, bool gr
 
 template <int NN, int NL>
 hipError_t launch_col_adj_pair_inst(dim3 g, const Launch& la, hipStream_t s) {
-  const size_t dyn = col_adj_pair_lds(NN, NL);
+  const size_t dyn = col_adj_pair_lds(NN, NL, kRegGroup);
   const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col_adj_pair<NN, NL>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(dyn));

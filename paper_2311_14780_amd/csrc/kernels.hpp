@@ -149,10 +149,12 @@ int rows_per_row_block(int N);
 int adj_part_stride(int N);
 // Positions per probe-gradient group that the column-adjoint instance of DFT
 // size nl allows for a job with M modes: 4 when an M x N x G accumulator fits
-// in LDS, else 2 (the paired instance, whose LDS holds two positions' Ohat)
-// where that instance exists and fits, else 1.  A job's group is the least
-// over its slots' sizes, and 1 for a job with an exact-ratio wavelength whose
-// least is 2 (the paired instance is zero-padded only).
+// in LDS, else kRegGroup (the grouped-position instance, which sums in
+// registers and whose LDS holds the group's Ohat) where that instance exists
+// and fits, else 1.  A job's group is the least over its slots' sizes, and 1
+// when some slot does not fit the grouped-position instance at that size (an
+// exact-ratio wavelength: that instance is zero-padded only).
+constexpr int kRegGroup = 3;
 int probe_group_of(int N, int M, int nl);
 // Groups of four only pay when the launch keeps enough blocks to fill the
 // GPU (two per CU): a job with fewer than this many (positions / 4 x column
@@ -164,10 +166,12 @@ int col_sets_adj(int N, int nl);
 // would give fewer than 1024 blocks (small objects: more, shorter blocks).
 int obj_tile_rows(int H, int W, int slots);
 constexpr int kObjTileW = 64;
-// The paired column-adjoint instance exists for (N, nl).
+// The grouped-position column-adjoint instance exists for (N, nl).
 bool pair_capable(int N, int nl);
-// Dynamic LDS bytes of the paired column-adjoint instance.
-size_t col_adj_pair_lds(int N, int nl);
+// Dynamic LDS bytes of the grouped-position column adjoint over pg positions.
+size_t col_adj_pair_lds(int N, int nl, int pg);
+// That instance exists for (N, nl) and its pg-position LDS fits a workgroup.
+bool pair_fits(int N, int nl, int pg);
 // Dynamic LDS bytes of the column-adjoint instance of DFT size nl for a job
 // with M modes (0 if the job's group is 1).
 size_t col_adj_lds_of(int N, int nl, int M, int group);
@@ -199,8 +203,8 @@ hipError_t launch_resample_T(int N, const Launch& la, long long units, hipStream
 // dL/d alpha (exact-ratio launches only)
 hipError_t launch_col_adj(int N, int nl, const Launch& la, long long units, size_t dyn_lds,
                           bool grouped, bool ratio, hipStream_t s);
-// Paired column adjoint (jobs whose probe-gradient group is 2; zero-padded
-// DFT sizes of N >= 256 only, see pair_capable).
+// Grouped-position column adjoint (jobs whose probe-gradient group is
+// kRegGroup; zero-padded DFT sizes of N >= 256 only, see pair_capable).
 hipError_t launch_col_adj_pair(int N, int nl, const Launch& la, long long units, hipStream_t s);
 hipError_t launch_row_adj(int N, const Launch& la, long long units, hipStream_t s);
 

@@ -1,13 +1,15 @@
-"""GPU parity of the paired column adjoint: jobs whose [M][N][G] probe-gradient
-accumulator does not fit in LDS sum the terms of two consecutive positions
-per block (probe-gradient groups of two).
+"""GPU parity of the grouped-position column adjoint: jobs whose [M][N][G]
+probe-gradient accumulator does not fit in LDS sum the terms of three
+consecutive positions per block in registers (probe-gradient groups of
+three).
 
 N = 256 with 5 modes: at DFT size 300 (16-column blocks) the accumulator
-needs 5 x 256 x 16 x 8 B = 160 KiB, more than a block's LDS, while two
-positions' Ohat (64 KiB) next to the transform buffer (40 KiB) fit, so the
-job takes groups of two; its other DFT size, 343 (8-column blocks), then runs
-the paired instance as well.  An odd number of positions leaves a group with
-one position at the end of the scan.  Checked against the FP64 oracle, for
+needs 5 x 256 x 16 x 8 B = 160 KiB, more than a block's LDS, while three
+positions' Ohat (96 KiB) next to the transform buffer and twiddles (44 KiB)
+fit, so the job takes groups of three; its other DFT size, 343 (8-column
+blocks), then runs the grouped-position instance as well.  Position counts
+that are not multiples of three leave a short group (one position at K = 7,
+two at K = 5) at the end of the scan.  Checked against the FP64 oracle, for
 bitwise chunk invariance, and for bitwise equality alone and next to a job
 with groups of four in one call."""
 import numpy as np
@@ -43,7 +45,7 @@ def test_pairs_chunk_invariant():
     case = U.make_case(_workload(9), with_sigma=True, pads=(300, 343))
     prob = U.to_problem(case, DEV)
     whole = U.gpu_grads(prob)
-    for chunk in (3, 4):  # 3 is rounded up to a whole number of pairs
+    for chunk in (3, 4):  # 4 is rounded up to a whole number of groups (6)
         part = U.gpu_grads(prob, chunk=chunk)
         for k in KEYS:
             assert np.array_equal(np.asarray(whole[k]), np.asarray(part[k])), (chunk, k)
