@@ -109,10 +109,11 @@ __host__ __device__ constexpr int col_group_adj(int N, int nl) {
 __host__ __device__ constexpr int col_adj_lp(int N, int nl, int G) {
   return (N >= 384 && nl != 2 * N) ? G : G + 1;
 }
-// Row pitch of the paired column adjoint, whose waves each transform their
-// own columns of the buffer: an odd pitch spreads a column's elements over
-// the LDS banks (unpadded rows, 8 columns at N = 512: 254 ms per step of 5
-// harmonics x 8 modes against 158 ms with one element of padding).
+// Row pitch of the grouped-position column adjoint where its waves each
+// transform their own columns of the buffer: an odd pitch spreads a column's
+// elements over the LDS banks (unpadded rows, 8 columns at N = 512: 254 ms
+// per step of 5 harmonics x 8 modes against 158 ms with one element of
+// padding).  It bounds the instance's pitch at every size.
 __host__ __device__ constexpr int col_pair_lp(int G) { return G + 1; }
 // Threads per block of the column adjoint instance.
 __host__ __device__ constexpr int col_adj_threads(int N, int nl) { return CNT; }
@@ -1122,7 +1123,14 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
   constexpr int G = col_group_adj(N, NL);
   constexpr int AT = col_adj_threads(N, NL);
-  constexpr int LP = col_pair_lp(G);
+  // Each wave transforms its own columns, except at lengths that are
+  // multiples of 16 (radix-16 and -8 passes), whose strides along one column
+  // meet the same LDS banks at any odd pitch: those transform block-wide with
+  // unpadded rows (5 harmonics x 8 modes, N = 512: sizes 512 and 560 28.0 and
+  // 36.8 -> about 22 and 29 ms per launch; per wave everywhere: 151 ms, this
+  // mix 139.5 ms per step)
+  constexpr bool WAVE = NL % 16 != 0;
+  constexpr int LP = WAVE ? col_pair_lp(G) : G;
   constexpr int NE = N * G / AT;
   const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
@@ -1244,7 +1252,19 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
           if (mn < jb.M) zload(pn, mn);
         }
         __syncthreads();
-        fft_lines<NL, true, LW, 64, LP, true>(colw, twL, ld_w, st_w);
+        if constexpr (WAVE) {
+          fft_lines<NL, true, LW, 64, LP, true>(colw, twL, ld_w, st_w);
+        } else {
+          auto ld_t = [&](int line, int t) {
+            int u = t + N / 2;
+            if (u >= NL) u -= NL;
+            return u < N ? buf[u * LP + line] : make_float2(0.f, 0.f);
+          };
+          auto st_t = [&](int line, int t, float2 v) {
+            if (t < N) buf[t * LP + line] = cscale(v, ps);
+          };
+          fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_t, st_t);
+        }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
