@@ -1131,11 +1131,14 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   // mix 139.5 ms per step)
   constexpr bool WAVE = NL % 16 != 0;
   constexpr int LP = WAVE ? col_pair_lp(G) : G;
+  // the N-point transforms (object columns, gradient tail) run block-wide on
+  // unpadded rows at every length
+  constexpr int LPN = G;
   constexpr int NE = N * G / AT;
   const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
-  __shared__ float2 buf[NL * LP];
+  __shared__ float2 buf[NL * LP > N * LPN ? NL * LP : N * LPN];
   __shared__ float red[AT / 64];
   extern __shared__ float2 ohs[];  // [PG][N * G], element e of this thread at e = tid + q AT
   // The twiddle tables are copied to LDS and the transforms read them there:
@@ -1164,8 +1167,8 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   const float ps = jb.pad_scale[l];
   const size_t plane = static_cast<size_t>(N) * N;
   constexpr float invN = 1.0f / N;
-  auto ld_buf = [&](int line, int i) { return buf[i * LP + line]; };
-  auto st_buf = [&](int line, int i, float2 v) { buf[i * LP + line] = v; };
+  auto ld_buf = [&](int line, int i) { return buf[i * LPN + line]; };
+  auto st_buf = [&](int line, int i, float2 v) { buf[i * LPN + line] = v; };
   float2 o[PG][NE], go[PG][NE];
   float sig[PG], sgsum[PG] = {};
 
@@ -1178,18 +1181,18 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
       const gf2* __restrict__ ry = gmem(jb.ramp) + static_cast<size_t>(c) * 2 * N;
       sig[p] = jb.sigma ? gmem(jb.sigma)[k] : 1.0f;
       auto ld_x = [&](int line, int i) { return ldv(X, i * N + line); };
-      auto st_ramp = [&](int line, int i, float2 v) { buf[i * LP + line] = cmul(v, ldv(ry, i)); };
-      fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_x, st_ramp);
+      auto st_ramp = [&](int line, int i, float2 v) { buf[i * LPN + line] = cmul(v, ldv(ry, i)); };
+      fft_lines<N, false, G, AT, LPN, true>(buf, twN, ld_x, st_ramp);
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = tid + q * AT, line = e % G, i = e / G;
-        ohs[p * N * G + e] = buf[i * LP + line];
+        ohs[p * N * G + e] = buf[i * LPN + line];
       }
-      fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
+      fft_lines<N, true, G, AT, LPN, true>(buf, twN, ld_buf, st_buf);
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = tid + q * AT, line = e % G, i = e / G;
-        o[p][q] = cscale(buf[i * LP + line], invN);
+        o[p][q] = cscale(buf[i * LPN + line], invN);
         go[p][q] = make_float2(0.f, 0.f);
       }
       __syncthreads();
@@ -1308,24 +1311,24 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = tid + q * AT, line = e % G, i = e / G;
-        buf[i * LP + line] = go[p][q];
+        buf[i * LPN + line] = go[p][q];
       }
       __syncthreads();
-      fft_lines<N, false, G, AT, LP, true>(buf, twN, ld_buf, st_buf);
+      fft_lines<N, false, G, AT, LPN, true>(buf, twN, ld_buf, st_buf);
       float dsum = 0.f;
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = tid + q * AT, line = e % G, i = e / G;
-        const float2 gh = buf[i * LP + line];
+        const float2 gh = buf[i * LPN + line];
         const float2 oh = ohs[p * N * G + e];
         const float nu = 2.0f * static_cast<float>(kPi) * freq(i, N);
         dsum += nu * (gh.y * oh.x - gh.x * oh.y);
-        buf[i * LP + line] = cmul(gh, cconj(ldv(ry, i)));
+        buf[i * LPN + line] = cmul(gh, cconj(ldv(ry, i)));
       }
       __syncthreads();
       gf2* __restrict__ GX = gmem(jb.GX) + (static_cast<size_t>(c) * jb.L + l) * plane + x0;
       auto st_gx = [&](int line, int i, float2 v) { stv(GX, i * N + line, cscale(v, invN)); };
-      fft_lines<N, true, G, AT, LP, true>(buf, twN, ld_buf, st_gx);
+      fft_lines<N, true, G, AT, LPN, true>(buf, twN, ld_buf, st_gx);
       const float s = block_sum<AT>(dsum, red);
       if (tid == 0) gmem(jb.dy_part)[slot] = s * invN;
     }
