@@ -1800,7 +1800,7 @@ constexpr int kProbeGroup = 4;
 constexpr size_t kColAdjLds = 156 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one workgroup
 
-// Zero-padded DFT sizes of N >= 256 have a paired column-adjoint instance.
+// Zero-padded DFT sizes of N >= 256 have a grouped-position column-adjoint instance.
 bool pair_capable(int N, int nl) { return N >= 256 && nl != czt_len(N); }
 
 int probe_group_of(int N, int M, int nl) {
