@@ -191,9 +191,10 @@ int32_t ptycho_supported(int32_t N, int32_t pad);
    Any workspace of at least the chunk = 1 size works; a larger workspace
    lets the library process more positions per launch.  Loss + gradient
    calls that want the probe gradient sum it over groups of consecutive
-   positions of a job (4 when the sums fit in on-chip memory and the scan
-   is long enough to keep the launch filled, 3 when they do not fit, else 1;
-   a function of the job alone), so for them `chunk` is rounded up to a
+   positions of a job (3 at windows of 384 and 512 pixels and wherever the
+   sums of 4 do not fit in on-chip memory, 4 when they fit and the scan is
+   long enough to keep the launch filled, else 1; a function of the job
+   alone), so for them `chunk` is rounded up to a
    multiple of the job's group size.  Only the size fields
    (K, L, M, N, H, W, pad, ratio) and whether rs_idx is non-NULL are read: the array
    pointers may be NULL, so a scheduler can size a call before allocating. */

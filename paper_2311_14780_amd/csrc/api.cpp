@@ -383,14 +383,20 @@ int job_probe_group(const ptycho_job_t& j, bool want_probe) {
     g = std::min(g, probe_group_of(j.N, j.M, eff_pad(j, l)));
     sets = std::min(sets, col_sets_adj(j.N, eff_pad(j, l)));
   }
+  // register groups run the grouped-position instance on every wavelength:
+  // each must have it and fit it, else the job takes LDS groups where every
+  // wavelength fits them (a job with an exact-ratio wavelength)
+  if (g == kRegGroup) {
+    bool reg = true, lds = true;
+    for (int l = 0; l < j.L; ++l) {
+      reg = reg && pair_fits(j.N, eff_pad(j, l), kRegGroup);
+      lds = lds && lds_group_fits(j.N, j.M, eff_pad(j, l));
+    }
+    if (!reg) g = lds ? kProbeGroup : 1;
+  }
   // small scans: one position per block keeps the column adjoint's launch
   // filled (100 positions at N = 64: 100 -> 400 blocks)
-  if (g >= 4 && static_cast<long long>((j.K + g - 1) / g) * sets < kMinGroupedBlocks) g = 1;
-  // register groups run the grouped-position instance on every wavelength:
-  // each must have it and fit it
-  if (g == kRegGroup)
-    for (int l = 0; l < j.L; ++l)
-      if (!pair_fits(j.N, eff_pad(j, l), kRegGroup)) return 1;
+  if (g >= kProbeGroup && static_cast<long long>((j.K + g - 1) / g) * sets < kMinGroupedBlocks) g = 1;
   return g;
 }
 

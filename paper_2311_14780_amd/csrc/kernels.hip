@@ -1794,7 +1794,6 @@ int rows_per_adj_block(int N) { return N <= 128 ? 16 : (N == 512 ? 4 : 8); }
 int rows_per_row_block(int N) { return N == 64 ? 32 : (N <= 256 ? 16 : 8); }
 int adj_part_stride(int N) { return adj_stride(N); }
 
-constexpr int kProbeGroup = 4;
 // LDS a column-adjoint block may use (gfx950: 160 KB per workgroup), less a
 // margin for the reduction scratch.
 constexpr size_t kColAdjLds = 156 * 1024;
@@ -1803,11 +1802,20 @@ constexpr size_t kLdsMax = 160 * 1024;  // LDS of one workgroup
 // Zero-padded DFT sizes of N >= 256 have a grouped-position column-adjoint instance.
 bool pair_capable(int N, int nl) { return N >= 256 && nl != czt_len(N); }
 
-int probe_group_of(int N, int M, int nl) {
+bool lds_group_fits(int N, int M, int nl) {
   const size_t G = static_cast<size_t>(col_group_adj(N, nl));
   const size_t acc = static_cast<size_t>(M) * N * G * sizeof(float2);
   const size_t buf = static_cast<size_t>(nl) * col_adj_lp(N, nl, static_cast<int>(G)) * sizeof(float2);
-  if (acc + buf <= kColAdjLds) return kProbeGroup;
+  return acc + buf <= kColAdjLds;
+}
+
+int probe_group_of(int N, int M, int nl) {
+  // at N >= 384 register groups of three beat LDS groups of four where both
+  // fit (3 harmonics x 4 modes at N = 384: column adjoint 13.9 -> 12.2 ms,
+  // probe reduction 0.55 -> 0.73 ms per step); at N = 256 they do not
+  // (4 x 3 modes: 2.45 -> 3.03 ms)
+  if (N >= 384 && pair_fits(N, nl, kRegGroup)) return kRegGroup;
+  if (lds_group_fits(N, M, nl)) return kProbeGroup;
   if (pair_fits(N, nl, kRegGroup)) return kRegGroup;
   return 1;
 }

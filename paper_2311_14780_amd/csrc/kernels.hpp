@@ -148,13 +148,17 @@ int rows_per_row_block(int N);
 // alpha parts are [C][L][stride]).
 int adj_part_stride(int N);
 // Positions per probe-gradient group that the column-adjoint instance of DFT
-// size nl allows for a job with M modes: 4 when an M x N x G accumulator fits
-// in LDS, else kRegGroup (the grouped-position instance, which sums in
-// registers and whose LDS holds the group's Ohat) where that instance exists
-// and fits, else 1.  A job's group is the least over its slots' sizes, and 1
+// size nl allows for a job with M modes: kRegGroup (the grouped-position
+// instance, which sums in registers and whose LDS holds the group's Ohat) at
+// N >= 384 where that instance fits, else 4 when an M x N x G accumulator
+// fits in LDS, else kRegGroup where that instance fits, else 1.  A job's group is the least over its slots' sizes, and 1
 // when some slot does not fit the grouped-position instance at that size (an
 // exact-ratio wavelength: that instance is zero-padded only).
 constexpr int kRegGroup = 3;
+constexpr int kProbeGroup = 4;  // positions of an LDS group
+// The [M][N][G] LDS accumulator of a group of kProbeGroup fits next to the
+// transform buffer of the column-adjoint instance of DFT size nl.
+bool lds_group_fits(int N, int M, int nl);
 int probe_group_of(int N, int M, int nl);
 // Groups of four only pay when the launch keeps enough blocks to fill the
 // GPU (two per CU): a job with fewer than this many (positions / 4 x column

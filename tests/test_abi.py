@@ -87,6 +87,19 @@ def test_workspace_bytes_scale_with_chunk():
     assert _ws_bytes(big, which=0, chunk=1)[1] < _ws_bytes(big, which=0, chunk=2)[1]
 
 
+def test_probe_group_choice_at_n384():
+    # zero-padded wavelengths at N = 384: register groups of three
+    pad = _job(K=900, L=2, M=4, N=384, H=1024, W=1024, pads=(420, 480))
+    assert _ws_bytes(pad, chunk=1) == _ws_bytes(pad, chunk=3)
+    assert _ws_bytes(pad, chunk=3)[1] < _ws_bytes(pad, chunk=4)[1]
+    # one exact-ratio wavelength (no grouped-position instance): LDS groups of
+    # four, which both wavelengths fit
+    mixed = _job(K=900, L=2, M=2, N=384, H=1024, W=1024, pads=(420, 0))
+    mixed.ratio[1] = 401.5
+    assert _ws_bytes(mixed, chunk=1) == _ws_bytes(mixed, chunk=4)
+    assert _ws_bytes(mixed, chunk=4)[1] < _ws_bytes(mixed, chunk=5)[1]
+
+
 @pytest.mark.parametrize("change,code", [
     (dict(L=0), B.PTYCHO_EINVAL), (dict(L=9), B.PTYCHO_EINVAL), (dict(M=0), B.PTYCHO_EINVAL),
     (dict(K=-1), B.PTYCHO_EINVAL), (dict(N=100), B.PTYCHO_EUNSUPPORTED),

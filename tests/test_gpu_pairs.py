@@ -75,3 +75,25 @@ def test_pairs_alone_and_next_to_a_grouped_job():
             if k == "loss":
                 v = float(v[0])
             assert np.array_equal(np.asarray(ref[k]), np.asarray(v)), k
+
+
+def _n384(K, M=2):
+    weights = tuple(0.5 ** m for m in range(M))
+    return synth.reduced(synth.get_workload("C5"), L=2, M=M, harmonics=(19, 23),
+                         mode_weights=weights, K=K, name="C5-groups")
+
+
+def test_n384_register_groups_and_lds_groups_beside_an_exact_ratio():
+    # zero-padded wavelengths at N = 384 take register groups of three (a
+    # short group of one at K = 7); with one exact-ratio wavelength, which has
+    # no grouped-position instance, the job takes LDS groups of four
+    for pads in ((420, 480), (420, 384 * 23 / 19)):
+        case = U.make_case(_n384(7), with_sigma=True, pads=pads)
+        print("N=384 pads", case["pads"], flush=True)
+        prob = U.to_problem(case, DEV)
+        got = U.gpu_grads(prob, kind=0)
+        ref = U.oracle_grads(case, kind=0)
+        print("  ", U.compare(got, ref), flush=True)
+        part = U.gpu_grads(prob, chunk=3)
+        for k in KEYS:
+            assert np.array_equal(np.asarray(got[k]), np.asarray(part[k])), (pads, k)
