@@ -904,7 +904,11 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), adj_narrow(N, NL) ? 4 : 2) 
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
   const bool want_probe = jb.g_probe != nullptr;
-  constexpr int LP = col_adj_lp(N, NL, G);
+  // the Bluestein length 768 at N = 384 without the distance gradient: unpadded
+  // rows too (its one instance that does not spill then; 3 harmonics x 4
+  // modes, exact ratio: column adjoint 22.6 -> 21.3 ms per step).  The host's
+  // LDS budget uses col_adj_lp, the larger pitch.
+  constexpr int LP = (NL == czt_nb<N>() && N == 384 && !RATIO) ? G : col_adj_lp(N, NL, G);
   constexpr int NE = N * G / AT;
   __shared__ float2 buf[NL * LP];
   __shared__ float red[AT / 64];
