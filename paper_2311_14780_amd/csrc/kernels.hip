@@ -109,12 +109,13 @@ __host__ __device__ constexpr int col_group_adj(int N, int nl) {
 __host__ __device__ constexpr int col_adj_lp(int N, int nl, int G) {
   return (N >= 384 && nl != 2 * N) ? G : G + 1;
 }
-// Row pitch of the grouped-position column adjoint where its waves each
-// transform their own columns of the buffer: an odd pitch spreads a column's
-// elements over the LDS banks (unpadded rows, 8 columns at N = 512: 254 ms
-// per step of 5 harmonics x 8 modes against 158 ms with one element of
-// padding).  It bounds the instance's pitch at every size.
-__host__ __device__ constexpr int col_pair_lp(int G) { return G + 1; }
+// Row pitch of the grouped-position column adjoint's transposed tile: the
+// detector rows' pitch (with their skew at lengths that are multiples of 16),
+// padded to 32 / G modulo 32 so that the coalesced tile stores and reads
+// (G rows x 32 / G elements per half-wave) meet distinct banks.
+__host__ __device__ constexpr int pair_row_pitch(int nl, int G) {
+  return row_lp(nl) + ((32 / G - row_lp(nl) % 32) + 32) % 32;
+}
 // Threads per block of the column adjoint instance.
 __host__ __device__ constexpr int col_adj_threads(int N, int nl) { return CNT; }
 // Row stride of the column adjoint's per-block partial sums ([C][L][stride]):
@@ -1127,14 +1128,15 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   static_assert(NL != czt_nb<N>(), "zero-padded sizes only");
   constexpr int G = col_group_adj(N, NL);
   constexpr int AT = col_adj_threads(N, NL);
-  // Each wave transforms its own columns, except at lengths that are
-  // multiples of 16 (radix-16 and -8 passes), whose strides along one column
-  // meet the same LDS banks at any odd pitch: those transform block-wide with
-  // unpadded rows (5 harmonics x 8 modes, N = 512: sizes 512 and 560 28.0 and
-  // 36.8 -> about 22 and 29 ms per launch; per wave everywhere: 151 ms, this
-  // mix 139.5 ms per step)
-  constexpr bool WAVE = NL % 16 != 0;
-  constexpr int LP = WAVE ? col_pair_lp(G) : G;
+  // The Z tile of a transform is stored transposed, one column per LDS row
+  // in the detector rows' layout, and each wave transforms its own rows
+  // (wave fences only).  Columns left in place instead need an odd pitch
+  // (unpadded: 254 ms per step of 5 harmonics x 8 modes at N = 512, against
+  // 158 ms), and at lengths that are multiples of 16 their radix-16 and -8
+  // strides meet the same banks at any odd pitch, so those sizes transformed
+  // block-wide: 137.7 ms for that mix, 135.7 ms with the transposed tile.
+  constexpr int LPC = pair_row_pitch(NL, G);
+  using TI = Lds<NL, LPC, false>;
   // the N-point transforms (object columns, gradient tail) run block-wide on
   // unpadded rows at every length
   constexpr int LPN = G;
@@ -1142,7 +1144,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
   const UnitRef r = decode_cols<N / G>(la);
   const JobDev& jb = *r.jb;
   if (*gmem(jb.status)) return;
-  __shared__ float2 buf[NL * LP > N * LPN ? NL * LP : N * LPN];
+  __shared__ float2 buf[G * LPC > N * LPN ? G * LPC : N * LPN];
   __shared__ float red[AT / 64];
   extern __shared__ float2 ohs[];  // [PG][N * G], element e of this thread at e = tid + q AT
   // The twiddle tables are copied to LDS and the transforms read them there:
@@ -1223,15 +1225,15 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
       zt[q] = ldv(Zm, i * N + line);
     }
   };
-  // this wave's columns: element t of column j at colw[t LP + j]
-  lf2* const colw = (lf2*)buf + (tid >> 6) * LW;
+  // this wave's rows (columns j of the tile): element t at roww[TI::at(j, t)]
+  lf2* const roww = (lf2*)buf + (tid >> 6) * LW * LPC;
   auto ld_w = [&](int j, int t) {
     int u = t + N / 2;
     if (u >= NL) u -= NL;
-    return u < N ? ldv(colw, u * LP + j) : make_float2(0.f, 0.f);
+    return u < N ? ldv(roww, TI::at(j, u)) : make_float2(0.f, 0.f);
   };
   auto st_w = [&](int j, int t, float2 v) {
-    if (t < N) stv(colw, t * LP + j, cscale(v, ps));
+    if (t < N) stv(roww, TI::at(j, t), cscale(v, ps));
   };
   zload(0, 0);
   for (int m = 0; m < jb.M; ++m) {
@@ -1250,7 +1252,7 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * AT, line = e % G, i = e / G;
-          buf[i * LP + line] = zt[q];
+          buf[TI::at(line, i)] = zt[q];
         }
         {
           // the next transform's tile: the next position of this mode,
@@ -1259,24 +1261,12 @@ __global__ __launch_bounds__(col_adj_threads(N, NL), 2) void k_col_adj_pair(Laun
           if (mn < jb.M) zload(pn, mn);
         }
         __syncthreads();
-        if constexpr (WAVE) {
-          fft_lines<NL, true, LW, 64, LP, true>(colw, twL, ld_w, st_w);
-        } else {
-          auto ld_t = [&](int line, int t) {
-            int u = t + N / 2;
-            if (u >= NL) u -= NL;
-            return u < N ? buf[u * LP + line] : make_float2(0.f, 0.f);
-          };
-          auto st_t = [&](int line, int t, float2 v) {
-            if (t < N) buf[t * LP + line] = cscale(v, ps);
-          };
-          fft_lines<NL, true, G, AT, LP, true>(buf, twL, ld_t, st_t);
-        }
+        fft_lines<NL, true, LW, 64, LPC, false>(roww, twL, ld_w, st_w);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * AT, line = e % G, i = e / G;
-          const float2 chi = buf[i * LP + line];
+          const float2 chi = buf[TI::at(line, i)];
           const float2 pc = cmulconj(pm[q], chi);  // conj(P) chi
           go[p][q].x = fmaf(sig[p], pc.x, go[p][q].x);
           go[p][q].y = fmaf(sig[p], pc.y, go[p][q].y);
@@ -1843,7 +1833,9 @@ size_t col_adj_pair_lds(int N, int nl, int pg) {
 bool pair_fits(int N, int nl, int pg) {
   if (!pair_capable(N, nl)) return false;
   const size_t G = static_cast<size_t>(col_group_adj(N, nl));
-  const size_t stat = (static_cast<size_t>(nl) * col_pair_lp(static_cast<int>(G)) + nl + N) * sizeof(float2) + 64;
+  const size_t tile = static_cast<size_t>(G) * pair_row_pitch(nl, static_cast<int>(G));
+  const size_t nbuf = static_cast<size_t>(N) * G;
+  const size_t stat = ((tile > nbuf ? tile : nbuf) + nl + N) * sizeof(float2) + 64;
   return col_adj_pair_lds(N, nl, pg) + stat <= kLdsMax;
 }
 
